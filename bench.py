@@ -1,0 +1,281 @@
+#!/usr/bin/env python3
+"""Benchmark of the tetrahedron-DOS hot path on one MI355X.
+
+Workload (default): 64^3 periodic k-grid (1,572,864 tetrahedra), 8 bands x 8 orbitals, 1000
+equidistant energies, FP32 band energies and orbital weights in structure-of-arrays layout, from the
+seeded random tight-binding model in ``synth`` (a stand-in for the paper's FeSe model, whose hopping
+parameters are not published). Inputs are resident in HBM before timing starts.
+
+One step = one forward pass (DOS) plus one backward pass (gradients with respect to band energies
+and orbital weights for G = 2 (DOS - DOS_target), the loss of the differentiation workload). The
+headline value counts dense-equivalent tetrahedron-band-energy updates, N_tet * nb * ne per pass,
+the work the paper's kernel visits; the JSON line also carries the plain-forward rate, the
+in-window update rate, a roofline object for the dominant kernel and the FP64 oracle's CPU rate on a
+bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode fwdbwd|fwd] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+PEAK_FP32_VALU_TFLOPS = 157.3  # MI355X published FP32 vector peak
+PEAK_HBM_GBS = 8000.0
+WORKLOAD = "k64_b8_e1000"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1710_10789_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(os.path.basename(p).encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def table1_offsets():
+    # Table I (Sec. III.B), corner label L = 1 + o1 + 2*o2 + 4*o3
+    rows = [(1, 2, 3, 6), (2, 3, 4, 6), (1, 3, 5, 6), (3, 4, 6, 8), (3, 5, 6, 7), (3, 6, 7, 8)]
+    return [[((L - 1) & 1, ((L - 1) >> 1) & 1, ((L - 1) >> 2) & 1) for L in r] for r in rows]
+
+
+def count_window_updates(eps, grid, e0, de, ne):
+    """Number of (tetrahedron, band, energy) triples with E1 < E_j < E4: the in-window work."""
+    n1, n2, n3 = grid
+    nb = eps.shape[0]
+    e = eps.reshape(nb, n1, n2, n3).astype(np.float64)
+    total = 0
+    for tet in table1_offsets():
+        lo = None
+        hi = None
+        for o in tet:
+            c = np.roll(e, shift=(-o[0], -o[1], -o[2]), axis=(1, 2, 3))
+            lo = c if lo is None else np.minimum(lo, c)
+            hi = c if hi is None else np.maximum(hi, c)
+        ok = np.isfinite(lo) & np.isfinite(hi)
+        lo, hi = lo[ok], hi[ok]
+        # first j with E_j > lo, last j with E_j < hi; refine the float guesses exactly
+        jlo = np.clip(np.floor((lo - e0) / de), 0, ne).astype(np.int64)
+        jlo -= (jlo > 0) & (e0 + (jlo - 1) * de > lo)
+        jlo += (jlo < ne) & (e0 + jlo * de <= lo)
+        jhi = np.clip(np.ceil((hi - e0) / de), -1, ne - 1).astype(np.int64)
+        jhi += (jhi < ne - 1) & (e0 + (jhi + 1) * de < hi)
+        jhi -= (jhi >= 0) & (e0 + jhi * de >= hi)
+        total += int(np.maximum(jhi - jlo + 1, 0).sum())
+    return total
+
+
+def algorithmic_flops(uwin, norb):
+    """Per in-window update: forward 4*norb FMAs + 4 corner cubics (8*norb + 24 flops); backward the
+    orbital sums s_c and dL/db (16*norb), 4 weights (24), 16 cubic partials (96), a 16-term
+    contraction (32)."""
+    return uwin * (8 * norb + 24), uwin * (16 * norb + 152)
+
+
+def algorithmic_bytes(nk, nb, norb, ne):
+    fwd = 4 * nk * nb + 4 * nk * nb * norb + 4 * ne * norb
+    bwd = fwd + 4 * nk * nb + 4 * nk * nb * norb
+    return fwd, bwd
+
+
+def load_traffic(kernel):
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f).get(kernel)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_sha") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(eps, w, grid, e0, de, ne, mode, G, gpu_fn):
+    """The FP64 oracle timed on the host cores on the same inputs (a full pass is ~10 s of CPU work:
+    its forward splits over k-slabs, its backward over bands, so both legs get min(cores, nb)
+    threads)."""
+    import oracle
+
+    oracle.build()
+    nb = eps.shape[0]
+    cores = min(len(os.sched_getaffinity(0)), nb)
+    n1, n2, n3 = grid
+    dense = 6 * n1 * n2 * n3 * nb * ne
+    t0 = time.perf_counter()
+    ref, _ = oracle.dos(eps, w, grid, e0, de, ne, nthreads=cores)
+    t1 = time.perf_counter()
+    if mode == "fwdbwd":
+        oracle.dos_backward(eps, w, grid, e0, de, G, nthreads=cores)
+    t2 = time.perf_counter()
+    got = gpu_fn()
+    err = float(np.abs(got - ref).max() / np.abs(ref).max())
+    return {
+        "value": dense / (t2 - t0),
+        "unit": "updates/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"the whole workload, one {'forward + backward' if mode == 'fwdbwd' else 'forward'} pass "
+                  f"(fwd {t1 - t0:.2f} s, bwd {t2 - t1:.2f} s), FP64",
+        "fwd_value": dense / (t1 - t0),
+        "gpu_fwd_err_vs_oracle": err,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--mode", choices=["fwdbwd", "fwd"], default="fwdbwd")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a device-to-device copy of 256 MiB (5 times) to scale HBM byte counters")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the tetrahedron DOS path is built and timed on a single "
+              "MI355X (--gpus 1); multi-GPU sharding is described, not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1710_10789_amd as tetra
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        n = 64 * 1024 * 1024  # floats: 256 MiB read + 256 MiB written per copy
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 5}), flush=True)
+        return
+    c = synth.config(WORKLOAD)
+    grid, norb, ne = c["grid"], c["norb"], c["ne"]
+    eps_np, w_np = synth.band_structure(norb, c["seed"], grid)
+    teps_np, tw_np = synth.band_structure(norb, 1, grid)  # target model of the loss
+    e0, de = synth.energy_grid(eps_np, ne)  # the headline workload's own grid; target DOS on it
+    nb, nk = eps_np.shape
+    n_tet = 6 * nk
+    dense = n_tet * nb * ne
+    uwin = count_window_updates(eps_np, grid, e0, de, ne)
+    f_fwd, f_bwd = algorithmic_flops(uwin, norb)
+    b_fwd, b_bwd = algorithmic_bytes(nk, nb, norb, ne)
+
+    eps = torch.from_numpy(eps_np).to(dev)
+    w = torch.from_numpy(w_np).to(dev)
+    target = tetra.dos_forward(torch.from_numpy(teps_np).to(dev), torch.from_numpy(tw_np).to(dev), grid, e0, de, ne)
+    dos = torch.empty((ne, norb), dtype=torch.float32, device=dev)
+    tetra.dos_forward(eps, w, grid, e0, de, ne, out=dos)
+    G = (2.0 * (dos - target)).contiguous()
+    ge = torch.empty_like(eps)
+    gw = torch.empty_like(w)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream(dev)
+    use_bwd = args.mode == "fwdbwd"
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        tetra.dos_forward(eps, w, grid, e0, de, ne, out=dos)
+        if ev is not None:
+            ev[1].record(stream)
+        if use_bwd:
+            tetra.dos_backward(eps, w, grid, e0, de, G, grad_eps=ge, grad_w=gw)
+            if ev is not None:
+                ev[2].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(events[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fwd_ms = np.array([e[0].elapsed_time(e[1]) for e in events])
+    bwd_ms = np.array([e[1].elapsed_time(e[2]) for e in events]) if use_bwd else np.zeros(args.steps)
+    ms_per_step = wall * 1e3 / args.steps
+    t_fwd = float(fwd_ms.mean()) * 1e-3
+    t_bwd = float(bwd_ms.mean()) * 1e-3
+
+    if use_bwd and t_bwd > t_fwd:
+        kname, flops, t_k = "dos_backward_kernel", f_bwd, t_bwd
+    else:
+        kname, flops, t_k = "dos_forward_kernel", f_fwd, t_fwd
+    achieved = flops / t_k / 1e12
+    roofline = {
+        "bound": "alu",
+        "kernel": kname,
+        "achieved": achieved,
+        "peak": PEAK_FP32_VALU_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": achieved / PEAK_FP32_VALU_TFLOPS,
+        "traffic": load_traffic(kname),
+        "algorithmic_flops_per_launch": flops,
+        "avg_launch_ms": t_k * 1e3,
+    }
+
+    out = {
+        "metric": "tetra-band-energy updates/s at 64^3 k, 8 bands, 1000 E; fwd+bwd vs plain fwd",
+        # dense-equivalent (tetrahedron, band, energy) triples of the workload per second of a step
+        "value": dense / (ms_per_step * 1e-3),
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded random 8-orbital tight-binding model; eigh on the host, untimed)",
+        "config": {
+            "workload": f"{WORKLOAD}: 64^3 periodic k-grid, 8 bands x 8 orbitals, 1000 energies, FP32 SoA",
+            "step": "forward + backward" if use_bwd else "forward",
+            "n_tetrahedra": n_tet,
+            "dense_updates_per_pass": dense,
+            "in_window_updates_per_pass": uwin,
+        },
+        "fwd_ms": t_fwd * 1e3,
+        "bwd_ms": t_bwd * 1e3 if use_bwd else None,
+        "fwd_updates_per_s": dense / t_fwd,
+        "fwdbwd_updates_per_s": dense / (t_fwd + t_bwd) if use_bwd else None,
+        "fwdbwd_over_fwd": (dense / (t_fwd + t_bwd)) / (dense / t_fwd) if use_bwd else None,
+        "in_window_updates_per_s_fwd": uwin / t_fwd,
+        "roofline": roofline,
+        "roofline_fwd": {"achieved": f_fwd / t_fwd / 1e12, "frac": f_fwd / t_fwd / 1e12 / PEAK_FP32_VALU_TFLOPS,
+                         "hbm_gbs_algorithmic": b_fwd / t_fwd / 1e9},
+        "roofline_bwd": ({"achieved": f_bwd / t_bwd / 1e12, "frac": f_bwd / t_bwd / 1e12 / PEAK_FP32_VALU_TFLOPS,
+                          "hbm_gbs_algorithmic": b_bwd / t_bwd / 1e9} if use_bwd else None),
+        "kernel_source_sha": kernel_source_hash(),
+    }
+    if not args.no_cpu_baseline:
+        def gpu_fn():
+            torch.cuda.synchronize()
+            return dos.cpu().numpy().astype(np.float64)
+
+        out["cpu_baseline"] = cpu_baseline(eps_np, w_np, grid, e0, de, ne, args.mode,
+                                           G.cpu().numpy().astype(np.float64), gpu_fn)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

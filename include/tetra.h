@@ -1,0 +1,144 @@
+/*
+ * tetra.h -- C ABI of the MI355X (gfx950) tetrahedron-method density-of-states library.
+ *
+ * Paper: D. Guterding and H. O. Jeschke, "An efficient GPU algorithm for tetrahedron-based
+ * Brillouin-zone integration", arXiv:1710.10789.
+ *
+ * What the library computes (Sec. II, eqs. dos, tetracontriborbitalresolved, tetmethoorbitalresolved):
+ *
+ *   DOS[j][m] = sum over cubes of the periodic k-grid, over the six tetrahedra of Table I, over bands
+ *               n and over the four corners l of  b[n][m][k_l] * dw_{n,l}/dE (E_j)
+ *
+ * with the corner weights of the five energy cases of Sec. II.C, evaluated on the four corner
+ * energies of each tetrahedron-band sorted ascending, and E_j = e0 + j*de (an equidistant energy
+ * grid, Sec. IV.A). The inputs follow the paper's statement of the problem: band energies E_n(k)
+ * and orbital weights b_mn(k) = |a^m_n(k)|^2 (eq. matrixelements) on the k-grid, stored as
+ * linearised arrays (Sec. III.B).
+ *
+ * Conventions shared by every entry point:
+ *  - k-grid: n1 x n2 x n3 points, periodic, k = (i1*n2 + i2)*n3 + i3 (i3 fastest). Every grid point
+ *    is the corner 000 of one elemental cube. Corner label L of Table I (1..8) sits at offset
+ *    (o1, o2, o3) with L = 1 + o1 + 2*o2 + 4*o3 along axes (1, 2, 3).
+ *  - V_T/V_G = 1 / (6*n1*n2*n3); the DOS is per energy unit, per k-point (unit cell) and orbital;
+ *    no spin factor.
+ *  - Energy cases: E <= E1 and E >= E4 contribute nothing; (E1,E2], (E2,E3], (E3,E4) use the three
+ *    formula sets of Sec. II.C (the middle-case dw3/dE taken as the derivative of the printed w3).
+ *  - A tetrahedron-band with a non-finite corner energy contributes nothing.
+ *  - All array pointers are DEVICE pointers (memory from hipMalloc or a caching allocator on top of
+ *    it); the caller owns every buffer. Inputs are read-only; outputs are overwritten, never
+ *    accumulated. Calls are asynchronous on `stream` (a hipStream_t; NULL means the null stream) and
+ *    never synchronise the device.
+ *  - Errors: every entry point returns a tetra_status and never aborts or throws. Argument
+ *    validation happens on the host before any HIP call; on a validation failure nothing is
+ *    launched and outputs are untouched. A failed launch returns TETRA_ERR_HIP (the HIP error text
+ *    is available from tetra_last_hip_error()).
+ *  - Layouts are structure-of-arrays: eps[nb][nk], w[nb][norb][nk], dos[ne][norb].
+ *  - Limits: norb in 1..16 (the paper's largest realistic model, Sec. III.B); n1,n2,n3,nb,ne >= 1;
+ *    nb*nk < 2^31 and nb*norb*nk < 2^31; ne < 2^24; finite e0; finite de > 0.
+ */
+#ifndef TETRA_H
+#define TETRA_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TETRA_OK = 0,
+  TETRA_ERR_ARG = -1,         /* null pointer, bad size, bad grid, bad flag */
+  TETRA_ERR_UNSUPPORTED = -2, /* valid request the library does not implement (e.g. norb > 16) */
+  TETRA_ERR_WORKSPACE = -3,   /* workspace missing or too small */
+  TETRA_ERR_HIP = -4          /* a HIP runtime call or kernel launch failed */
+} tetra_status;
+
+/* Storage type of the orbital weights w. */
+typedef enum {
+  TETRA_W_F32 = 0, /* float w[nb][norb][nk]; w_scale must be NULL */
+  TETRA_W_F16 = 1  /* _Float16/half w[nb][norb][nk]; value = w * w_scale[n] (per band) */
+} tetra_wtype;
+
+/* Flag bits. */
+enum {
+  TETRA_KAHAN = 1u /* compensated (Kahan) FP32 accumulation of the per-workgroup histograms */
+};
+
+/* Problem descriptor (host memory). */
+typedef struct {
+  int n1, n2, n3; /* periodic k-grid, each >= 1 */
+  int nb;         /* bands, >= 1 */
+  int norb;       /* orbitals, 1..16 */
+  float e0, de;   /* energy grid E_j = e0 + j*de, de > 0 */
+  int ne;         /* number of energies, >= 1 */
+} tetra_desc;
+
+/*
+ * Orbital-resolved DOS (Sec. II.C, eq. tetmethoorbitalresolved).
+ *   d        host descriptor
+ *   eps      device, float [nb][nk]        band energies E_n(k)
+ *   w        device, [nb][norb][nk]        orbital weights b_mn(k) (type by wtype)
+ *   wtype    TETRA_W_F32 or TETRA_W_F16
+ *   w_scale  device, float [nb]            per-band scale for TETRA_W_F16, else NULL
+ *   dos      device, float [ne][norb]      result, overwritten
+ *   flags    0 or TETRA_KAHAN
+ *   stream   hipStream_t
+ * Allocates nothing.
+ */
+tetra_status tetra_dos_forward(const tetra_desc* d, const float* eps, const void* w, int wtype,
+                               const float* w_scale, float* dos, unsigned flags, void* stream);
+
+/*
+ * Adjoint of tetra_dos_forward for a scalar loss L with G = dL/dDOS (not in the paper; the
+ * derivative of the same sum with respect to its inputs).
+ *   grad_dos  device, float [ne][norb]     G
+ *   grad_eps  device, float [nb][nk]       dL/deps, overwritten; may be NULL
+ *   grad_w    device, float [nb][norb][nk] dL/dw (always FP32, of the dequantised weights),
+ *                                           overwritten; may be NULL
+ * At least one of grad_eps, grad_w must be non-NULL. Where an energy E_j equals a corner energy the
+ * loss is not differentiable; the one-sided value of the case containing E_j is returned.
+ * Allocates nothing.
+ */
+tetra_status tetra_dos_backward(const tetra_desc* d, const float* eps, const void* w, int wtype,
+                                const float* w_scale, const float* grad_dos, float* grad_eps,
+                                float* grad_w, unsigned flags, void* stream);
+
+/* One problem of a batch: its descriptor and device buffers (same meaning as tetra_dos_forward). */
+typedef struct {
+  tetra_desc d;
+  const float* eps;
+  const void* w;
+  const float* w_scale;
+  float* dos;
+} tetra_item;
+
+/*
+ * Bytes of device workspace tetra_dos_batched needs for these items (host array of n items).
+ * Returns 0 for invalid input.
+ */
+size_t tetra_dos_batched_workspace(const tetra_item* items, int n, int wtype, unsigned flags);
+
+/*
+ * Many independent problems (uneven grids, energy grids, band and orbital counts) in one
+ * persistent launch over a flattened work queue. `items` is host memory; `workspace` is device
+ * memory of at least tetra_dos_batched_workspace() bytes, owned by the caller and not used by
+ * anything else until the work on `stream` completes. Each item's dos is overwritten.
+ * Allocates nothing; the queue is written into the workspace with one host-to-device copy.
+ */
+tetra_status tetra_dos_batched(const tetra_item* items, int n, int wtype, unsigned flags,
+                               void* workspace, size_t ws_bytes, void* stream);
+
+/* Static text for a status code. */
+const char* tetra_status_string(int status);
+
+/* Text of the last HIP error seen by this library in the calling thread ("" if none). */
+const char* tetra_last_hip_error(void);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int tetra_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TETRA_H */

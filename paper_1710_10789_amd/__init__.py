@@ -1,0 +1,279 @@
+"""Tetrahedron-method orbital-resolved density of states on MI355X (gfx950).
+
+Python binding of the C-ABI library ``libtetra.so`` (declared in ``include/tetra.h``). This module
+only marshals arguments: it checks tensor shapes, dtypes and devices, and passes device pointers and
+the current HIP stream to the library. Every step of the computation runs in the library's HIP
+kernels. PyTorch provides device memory and streams.
+
+The library must have been built (``python -m paper_1710_10789_amd.build``); importing the functions
+below on a machine without it raises, there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = [
+    "TetraError",
+    "TETRA_KAHAN",
+    "TETRA_W_F32",
+    "TETRA_W_F16",
+    "library_path",
+    "lib",
+    "make_desc",
+    "dos_forward",
+    "dos_backward",
+    "dos",
+    "from_eigh",
+    "half_weights",
+]
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_PKG, "libtetra.so")
+
+TETRA_OK = 0
+TETRA_W_F32 = 0
+TETRA_W_F16 = 1
+TETRA_KAHAN = 1
+MAX_NORB = 16
+
+
+class TetraError(RuntimeError):
+    def __init__(self, func, status, detail=""):
+        self.status = status
+        msg = f"{func} failed: {_status_string(status)} ({status})"
+        if detail:
+            msg += f": {detail}"
+        super().__init__(msg)
+
+
+class TetraDesc(ctypes.Structure):
+    _fields_ = [
+        ("n1", ctypes.c_int),
+        ("n2", ctypes.c_int),
+        ("n3", ctypes.c_int),
+        ("nb", ctypes.c_int),
+        ("norb", ctypes.c_int),
+        ("e0", ctypes.c_float),
+        ("de", ctypes.c_float),
+        ("ne", ctypes.c_int),
+    ]
+
+
+class TetraItem(ctypes.Structure):
+    _fields_ = [
+        ("d", TetraDesc),
+        ("eps", ctypes.c_void_p),
+        ("w", ctypes.c_void_p),
+        ("w_scale", ctypes.c_void_p),
+        ("dos", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Load ``libtetra.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"{_LIB_PATH} is missing; build it with `python -m paper_1710_10789_amd.build`")
+        L = ctypes.CDLL(_LIB_PATH)
+        p, i, u = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint
+        L.tetra_dos_forward.argtypes = [ctypes.POINTER(TetraDesc), p, p, i, p, p, u, p]
+        L.tetra_dos_forward.restype = i
+        L.tetra_dos_backward.argtypes = [ctypes.POINTER(TetraDesc), p, p, i, p, p, p, p, u, p]
+        L.tetra_dos_backward.restype = i
+        L.tetra_dos_batched_workspace.argtypes = [ctypes.POINTER(TetraItem), i, i, u]
+        L.tetra_dos_batched_workspace.restype = ctypes.c_size_t
+        L.tetra_dos_batched.argtypes = [ctypes.POINTER(TetraItem), i, i, u, p, ctypes.c_size_t, p]
+        L.tetra_dos_batched.restype = i
+        L.tetra_status_string.argtypes = [i]
+        L.tetra_status_string.restype = ctypes.c_char_p
+        L.tetra_last_hip_error.argtypes = []
+        L.tetra_last_hip_error.restype = ctypes.c_char_p
+        L.tetra_version.argtypes = []
+        L.tetra_version.restype = i
+        _lib = L
+    return _lib
+
+
+def _status_string(status):
+    try:
+        return lib().tetra_status_string(int(status)).decode()
+    except Exception:  # noqa: BLE001 - message only
+        return "unknown status"
+
+
+def _check(func, status):
+    if status != TETRA_OK:
+        detail = lib().tetra_last_hip_error().decode() if status == -4 else ""
+        raise TetraError(func, status, detail)
+
+
+def make_desc(grid, nb, norb, e0, de, ne) -> TetraDesc:
+    n1, n2, n3 = (int(x) for x in grid)
+    return TetraDesc(n1, n2, n3, int(nb), int(norb), float(e0), float(de), int(ne))
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _stream_handle(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _require(t, name, shape, dtypes, device=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if t.dtype not in dtypes:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected one of {dtypes}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _shapes(eps, w, grid):
+    n1, n2, n3 = (int(x) for x in grid)
+    nk = n1 * n2 * n3
+    if eps.dim() != 2 or w.dim() != 3:
+        raise ValueError("eps must be [nb, nk] and w [nb, norb, nk]")
+    nb, norb = w.shape[0], w.shape[1]
+    return nk, nb, norb
+
+
+def dos_forward(eps, w, grid, e0, de, ne, *, w_scale=None, kahan=False, out=None):
+    """Orbital-resolved DOS ``[ne, norb]`` (FP32) on the current HIP stream.
+
+    eps: float32 ``[nb, nk]``; w: float32 or float16 ``[nb, norb, nk]`` (float16 needs ``w_scale``
+    float32 ``[nb]``); grid: (n1, n2, n3) with nk = n1*n2*n3; E_j = e0 + j*de.
+    """
+    torch = _torch()
+    nk, nb, norb = _shapes(eps, w, grid)
+    dev = eps.device
+    _require(eps, "eps", (nb, nk), (torch.float32,), dev)
+    _require(w, "w", (nb, norb, nk), (torch.float32, torch.float16), dev)
+    wtype = TETRA_W_F16 if w.dtype == torch.float16 else TETRA_W_F32
+    if wtype == TETRA_W_F16:
+        if w_scale is None:
+            raise ValueError("float16 weights need w_scale")
+        _require(w_scale, "w_scale", (nb,), (torch.float32,), dev)
+    elif w_scale is not None:
+        raise ValueError("w_scale is only used with float16 weights")
+    if out is None:
+        out = torch.empty((int(ne), norb), dtype=torch.float32, device=dev)
+    _require(out, "out", (int(ne), norb), (torch.float32,), dev)
+    d = make_desc(grid, nb, norb, e0, de, ne)
+    st = lib().tetra_dos_forward(
+        ctypes.byref(d), eps.data_ptr(), w.data_ptr(), wtype,
+        w_scale.data_ptr() if w_scale is not None else None, out.data_ptr(),
+        TETRA_KAHAN if kahan else 0, _stream_handle(dev))
+    _check("tetra_dos_forward", st)
+    return out
+
+
+def dos_backward(eps, w, grid, e0, de, grad_dos, *, w_scale=None, need_eps=True, need_w=True,
+                 grad_eps=None, grad_w=None):
+    """``(dL/deps [nb, nk] or None, dL/dw [nb, norb, nk] float32 or None)`` for ``grad_dos = dL/dDOS``."""
+    torch = _torch()
+    nk, nb, norb = _shapes(eps, w, grid)
+    dev = eps.device
+    ne = grad_dos.shape[0]
+    _require(eps, "eps", (nb, nk), (torch.float32,), dev)
+    _require(w, "w", (nb, norb, nk), (torch.float32, torch.float16), dev)
+    _require(grad_dos, "grad_dos", (ne, norb), (torch.float32,), dev)
+    wtype = TETRA_W_F16 if w.dtype == torch.float16 else TETRA_W_F32
+    if wtype == TETRA_W_F16:
+        _require(w_scale, "w_scale", (nb,), (torch.float32,), dev)
+    if need_eps and grad_eps is None:
+        grad_eps = torch.empty((nb, nk), dtype=torch.float32, device=dev)
+    if need_w and grad_w is None:
+        grad_w = torch.empty((nb, norb, nk), dtype=torch.float32, device=dev)
+    if grad_eps is not None:
+        _require(grad_eps, "grad_eps", (nb, nk), (torch.float32,), dev)
+    if grad_w is not None:
+        _require(grad_w, "grad_w", (nb, norb, nk), (torch.float32,), dev)
+    d = make_desc(grid, nb, norb, e0, de, ne)
+    st = lib().tetra_dos_backward(
+        ctypes.byref(d), eps.data_ptr(), w.data_ptr(), wtype,
+        w_scale.data_ptr() if w_scale is not None else None, grad_dos.data_ptr(),
+        grad_eps.data_ptr() if grad_eps is not None else None,
+        grad_w.data_ptr() if grad_w is not None else None, 0, _stream_handle(dev))
+    _check("tetra_dos_backward", st)
+    return grad_eps, grad_w
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class _TetraDOS(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, eps, w, grid, e0, de, ne, kahan):
+            ctx.save_for_backward(eps, w)
+            ctx.args = (tuple(grid), float(e0), float(de))
+            return dos_forward(eps.contiguous(), w.contiguous(), grid, e0, de, ne, kahan=kahan)
+
+        @staticmethod
+        def backward(ctx, g):
+            eps, w = ctx.saved_tensors
+            grid, e0, de = ctx.args
+            ge, gw = dos_backward(eps.contiguous(), w.contiguous(), grid, e0, de, g.contiguous(),
+                                  need_eps=ctx.needs_input_grad[0], need_w=ctx.needs_input_grad[1])
+            return ge, gw, None, None, None, None, None
+
+    return _TetraDOS
+
+
+_FN = None
+
+
+def dos(eps, w, grid, e0, de, ne, kahan=False):
+    """Differentiable orbital-resolved DOS ``[ne, norb]`` (FP32 weights).
+
+    Gradients with respect to ``eps`` and ``w`` come from the adjoint kernel.
+    """
+    global _FN
+    if _FN is None:
+        _FN = _autograd_function()
+    return _FN.apply(eps, w, tuple(grid), e0, de, ne, kahan)
+
+
+def from_eigh(evals, evecs):
+    """Structure-of-arrays inputs from ``torch.linalg.eigh`` output.
+
+    evals ``[nk, nb]`` and eigenvectors ``[nk, norb, nb]`` (columns are bands) -> eps ``[nb, nk]``,
+    w ``[nb, norb, nk]`` with w = |a|^2 (eq. matrixelements). Differentiable; not part of the DOS path.
+    """
+    eps = evals.transpose(0, 1).contiguous().float()
+    w = (evecs.real ** 2 + evecs.imag ** 2) if evecs.is_complex() else evecs ** 2
+    return eps, w.permute(2, 1, 0).contiguous().float()
+
+
+def half_weights(w):
+    """FP16 weights with a per-band power-of-two scale: ``(w16 [nb, norb, nk], scale [nb])``.
+
+    scale_n = 2^ceil(log2 max_{m,k} w[n, m, k]) (1 for an all-zero band), w16 = RNE(w / scale_n), so
+    the scaling itself is exact and the only error is FP16 rounding.
+    """
+    torch = _torch()
+    mx = w.abs().amax(dim=(1, 2)).double()
+    e = torch.where(mx > 0, torch.ceil(torch.log2(torch.where(mx > 0, mx, torch.ones_like(mx)))),
+                    torch.zeros_like(mx))
+    scale = torch.pow(2.0, e).float()
+    w16 = (w / scale[:, None, None]).to(torch.float16)
+    return w16.contiguous(), scale.contiguous()

@@ -1,0 +1,282 @@
+// Device-side building blocks of the tetrahedron DOS kernels (gfx950). Internal header.
+//
+// The corner weights implement the five energy cases of Sec. II.C of Guterding & Jeschke
+// (arXiv:1710.10789). The kernels use algebraically simplified forms of the printed formulas:
+//
+//   first case (E1 < E <= E2), x = E - E1, K = V / (E21 E31 E41), S = 1/E21 + 1/E31 + 1/E41:
+//       g1 = 4 K x^2 (3 - x S),   g_l = 4 K x^3 / E_l1  (l = 2, 3, 4)
+//   third case (E3 < E < E4), y = E4 - E, K' = V / (E41 E42 E43), S' = 1/E41 + 1/E42 + 1/E43:
+//       g_l = 4 K' y^3 / E_4l  (l = 1, 2, 3),   g4 = 4 K' y^2 (3 - y S')
+//   middle case (E2 < E <= E3): the printed C1, C2, C3 and their derivatives with z = E - E2,
+//       q = E3 - E, p = E4 - E, and the last term of dw3/dE taken as (C2 + C3)/E32, the form
+//       that is the energy derivative of the printed w3.
+//
+// with V = V_T / (4 V_G). Energies are handled in a local frame: x = E_j - E1 is formed once per
+// (tetrahedron, band, j) from e0 - E1 split into a head and an exact tail, so that the absolute
+// magnitude of the energies does not cost resolution.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tetra {
+
+// Table I: the six tetrahedra of an elemental cube by corner label L = 1 + o1 + 2*o2 + 4*o3, with
+// (o1, o2, o3) the corner's offsets along grid axes (1, 2, 3):
+//   {1,2,3,6} {2,3,4,6} {1,3,5,6} {3,4,6,8} {3,5,6,7} {3,6,7,8}
+// Returned as corner slots s = L - 1 in 4-bit fields (slot of the l-th corner at bits 4l..4l+2).
+// t is uniform across a wavefront, so the switch is a scalar branch.
+__device__ __forceinline__ uint32_t tet_slots(int t) {
+  switch (t) {
+    case 0: return 0x5210u;
+    case 1: return 0x5321u;
+    case 2: return 0x5420u;
+    case 3: return 0x7532u;
+    case 4: return 0x6542u;
+    default: return 0x7652u;
+  }
+}
+
+__device__ __forceinline__ bool finite4(float a, float b, float c, float d) {
+  return __builtin_isfinite(a) && __builtin_isfinite(b) && __builtin_isfinite(c) && __builtin_isfinite(d);
+}
+
+// Compare-exchange carrying an integer tag (corner slot) with the energy.
+__device__ __forceinline__ void cswap(float& ea, int& sa, float& eb, int& sb) {
+  const bool sw = eb < ea;
+  const float lo = sw ? eb : ea;
+  const float hi = sw ? ea : eb;
+  const int slo = sw ? sb : sa;
+  const int shi = sw ? sa : sb;
+  ea = lo;
+  eb = hi;
+  sa = slo;
+  sb = shi;
+}
+
+// Five-comparator network: ascending energies e[0..3] with their slots. Equal energies may end in
+// either order; the weights of corners with equal energies are equal, so the result does not depend
+// on it.
+__device__ __forceinline__ void sort4(float e[4], int s[4]) {
+  cswap(e[0], s[0], e[1], s[1]);
+  cswap(e[2], s[2], e[3], s[3]);
+  cswap(e[0], s[0], e[2], s[2]);
+  cswap(e[1], s[1], e[3], s[3]);
+  cswap(e[1], s[1], e[2], s[2]);
+}
+
+// a + b = hi + lo exactly (Knuth's two-sum).
+__device__ __forceinline__ void two_sum(float a, float b, float& hi, float& lo) {
+  hi = a + b;
+  const float bb = hi - a;
+  lo = (a - (hi - bb)) + (b - bb);
+}
+
+// Per (tetrahedron, band) constants of the corner-weight evaluation.
+struct TetSetup {
+  float d_hi, d_lo;            // e0 - E1 = d_hi + d_lo exactly
+  float e21, e31, e41;         // E2 - E1, E3 - E1, E4 - E1
+  float kA, sA;                // first case: K, S
+  float kC, sC;                // third case: K', S'
+  float r21, r31, r41, r32, r42, r43;
+  float k1, k2, k3;            // middle case: V/(E31 E41), V/(E31 E32 E41), V/(E32 E41 E42)
+};
+
+__device__ __forceinline__ TetSetup tet_setup(const float e[4], float e0, float V) {
+  TetSetup c;
+  two_sum(e0, -e[0], c.d_hi, c.d_lo);
+  c.e21 = e[1] - e[0];
+  c.e31 = e[2] - e[0];
+  c.e41 = e[3] - e[0];
+  const float e32 = e[2] - e[1], e42 = e[3] - e[1], e43 = e[3] - e[2];
+  // Reciprocals of zero differences are infinite; the case that would use them is never selected.
+  c.r21 = 1.0f / c.e21;
+  c.r31 = 1.0f / c.e31;
+  c.r41 = 1.0f / c.e41;
+  c.r32 = 1.0f / e32;
+  c.r42 = 1.0f / e42;
+  c.r43 = 1.0f / e43;
+  c.kA = V * c.r21 * c.r31 * c.r41;
+  c.sA = c.r21 + c.r31 + c.r41;
+  c.kC = V * c.r41 * c.r42 * c.r43;
+  c.sC = c.r41 + c.r42 + c.r43;
+  c.k1 = V * c.r31 * c.r41;
+  c.k2 = c.k1 * c.r32;
+  c.k3 = V * c.r32 * c.r41 * c.r42;
+  return c;
+}
+
+// x = E_j - E1 for E_j = e0 + j*de.
+__device__ __forceinline__ float local_x(const TetSetup& c, int j, float de) {
+  return __builtin_fmaf((float)j, de, c.d_hi) + c.d_lo;
+}
+
+// dw_l/dE at local energy x (0 < x < E41 assumed by the caller), sorted-corner order.
+__device__ __forceinline__ void corner_dos(const TetSetup& c, float x, float g[4]) {
+  if (x <= c.e21) {  // E1 < E <= E2
+    const float t = 4.0f * c.kA * x * x;
+    const float u = t * x;
+    g[0] = t * (3.0f - x * c.sA);
+    g[1] = u * c.r21;
+    g[2] = u * c.r31;
+    g[3] = u * c.r41;
+  } else if (x <= c.e31) {  // E2 < E <= E3
+    const float z = x - c.e21, q = c.e31 - x, p = c.e41 - x;
+    const float C1 = c.k1 * x * x, dC1 = 2.0f * c.k1 * x;
+    const float C2 = c.k2 * x * z * q, dC2 = c.k2 * (x * q + z * q - x * z);
+    const float C3 = c.k3 * z * z * p, dC3 = c.k3 * z * (2.0f * p - z);
+    const float S12 = C1 + C2, D12 = dC1 + dC2, S23 = C2 + C3, D23 = dC2 + dC3;
+    const float S123 = S12 + C3, D123 = D12 + dC3;
+    g[0] = dC1 + (D12 * q - S12) * c.r31 + (D123 * p - S123) * c.r41;
+    g[1] = D123 + (D23 * q - S23) * c.r32 + (dC3 * p - C3) * c.r42;
+    g[2] = (D12 * x + S12) * c.r31 + (D23 * z + S23) * c.r32;
+    g[3] = (D123 * x + S123) * c.r41 + (dC3 * z + C3) * c.r42;
+  } else {  // E3 < E < E4
+    const float y = c.e41 - x;
+    const float t = 4.0f * c.kC * y * y;
+    const float u = t * y;
+    g[0] = u * c.r41;
+    g[1] = u * c.r42;
+    g[2] = u * c.r43;
+    g[3] = t * (3.0f - y * c.sC);
+  }
+}
+
+// Corner weights g[4] (as corner_dos) and, for given multipliers s[4], the gradient
+// Eb[i] = d(sum_l s_l g_l)/dE_i with respect to the four sorted corner energies at fixed E, by reverse
+// accumulation through the same expressions as corner_dos.
+__device__ __forceinline__ void corner_dos_adjoint(const TetSetup& c, float V, float x, const float s[4], float g[4],
+                                                   float Eb[4]) {
+  if (x <= c.e21) {  // E1 < E <= E2
+    const float t = 4.0f * c.kA * x * x;
+    const float u = t * x;
+    g[0] = t * (3.0f - x * c.sA);
+    g[1] = u * c.r21;
+    g[2] = u * c.r31;
+    g[3] = u * c.r41;
+    float t_b = s[0] * (3.0f - x * c.sA);
+    float x_b = -s[0] * t * c.sA;
+    const float sA_b = -s[0] * t * x;
+    const float u_b = s[1] * c.r21 + s[2] * c.r31 + s[3] * c.r41;
+    float r21_b = s[1] * u, r31_b = s[2] * u, r41_b = s[3] * u;
+    t_b += u_b * x;
+    x_b += u_b * t;
+    const float kA_b = t_b * 4.0f * x * x;
+    x_b += t_b * 8.0f * c.kA * x;
+    r21_b += sA_b + kA_b * V * c.r31 * c.r41;
+    r31_b += sA_b + kA_b * V * c.r21 * c.r41;
+    r41_b += sA_b + kA_b * V * c.r21 * c.r31;
+    const float e21_b = -r21_b * c.r21 * c.r21, e31_b = -r31_b * c.r31 * c.r31, e41_b = -r41_b * c.r41 * c.r41;
+    Eb[0] = -(e21_b + e31_b + e41_b + x_b);
+    Eb[1] = e21_b;
+    Eb[2] = e31_b;
+    Eb[3] = e41_b;
+  } else if (x <= c.e31) {  // E2 < E <= E3
+    const float z = x - c.e21, q = c.e31 - x, p = c.e41 - x;
+    const float C1 = c.k1 * x * x, dC1 = 2.0f * c.k1 * x;
+    const float C2 = c.k2 * x * z * q, dC2 = c.k2 * (x * q + z * q - x * z);
+    const float C3 = c.k3 * z * z * p, dC3 = c.k3 * z * (2.0f * p - z);
+    const float S12 = C1 + C2, D12 = dC1 + dC2, S23 = C2 + C3, D23 = dC2 + dC3;
+    const float S123 = S12 + C3, D123 = D12 + dC3;
+    g[0] = dC1 + (D12 * q - S12) * c.r31 + (D123 * p - S123) * c.r41;
+    g[1] = D123 + (D23 * q - S23) * c.r32 + (dC3 * p - C3) * c.r42;
+    g[2] = (D12 * x + S12) * c.r31 + (D23 * z + S23) * c.r32;
+    g[3] = (D123 * x + S123) * c.r41 + (dC3 * z + C3) * c.r42;
+    // adjoints of the quantities the four outputs read
+    float dC1_b = s[0];
+    float D12_b = (s[0] * q + s[2] * x) * c.r31;
+    float S12_b = (s[2] - s[0]) * c.r31;
+    const float D123_b = s[0] * p * c.r41 + s[1] + s[3] * x * c.r41;
+    const float S123_b = (s[3] - s[0]) * c.r41;
+    const float D23_b = (s[1] * q + s[2] * z) * c.r32;
+    const float S23_b = (s[2] - s[1]) * c.r32;
+    float dC3_b = (s[1] * p + s[3] * z) * c.r42;
+    float C3_b = (s[3] - s[1]) * c.r42;
+    float q_b = s[0] * D12 * c.r31 + s[1] * D23 * c.r32;
+    float p_b = s[0] * D123 * c.r41 + s[1] * dC3 * c.r42;
+    float x_b = s[2] * D12 * c.r31 + s[3] * D123 * c.r41;
+    float z_b = s[2] * D23 * c.r32 + s[3] * dC3 * c.r42;
+    float r31_b = s[0] * (D12 * q - S12) + s[2] * (D12 * x + S12);
+    float r41_b = s[0] * (D123 * p - S123) + s[3] * (D123 * x + S123);
+    float r32_b = s[1] * (D23 * q - S23) + s[2] * (D23 * z + S23);
+    float r42_b = s[1] * (dC3 * p - C3) + s[3] * (dC3 * z + C3);
+    // partial sums
+    S12_b += S123_b;
+    C3_b += S123_b + S23_b;
+    D12_b += D123_b;
+    dC3_b += D123_b + D23_b;
+    const float C2_b = S23_b + S12_b;
+    const float dC2_b = D23_b + D12_b;
+    const float C1_b = S12_b;
+    dC1_b += D12_b;
+    // C3, dC3
+    const float k3_b = dC3_b * z * (2.0f * p - z) + C3_b * z * z * p;
+    z_b += dC3_b * c.k3 * (2.0f * p - 2.0f * z) + C3_b * 2.0f * c.k3 * z * p;
+    p_b += dC3_b * 2.0f * c.k3 * z + C3_b * c.k3 * z * z;
+    // C2, dC2
+    const float k2_b = dC2_b * (x * q + z * q - x * z) + C2_b * x * z * q;
+    x_b += dC2_b * c.k2 * (q - z) + C2_b * c.k2 * z * q;
+    q_b += dC2_b * c.k2 * (x + z) + C2_b * c.k2 * x * z;
+    z_b += dC2_b * c.k2 * (q - x) + C2_b * c.k2 * x * q;
+    // C1, dC1
+    float k1_b = dC1_b * 2.0f * x + C1_b * x * x;
+    x_b += dC1_b * 2.0f * c.k1 + C1_b * 2.0f * c.k1 * x;
+    // k1 = V r31 r41, k2 = k1 r32, k3 = V r32 r41 r42
+    k1_b += k2_b * c.r32;
+    r32_b += k2_b * c.k1 + k3_b * V * c.r41 * c.r42;
+    r41_b += k3_b * V * c.r32 * c.r42 + k1_b * V * c.r31;
+    const float r42_bb = r42_b + k3_b * V * c.r32 * c.r41;
+    r31_b += k1_b * V * c.r41;
+    const float e31_b = -r31_b * c.r31 * c.r31, e41_b = -r41_b * c.r41 * c.r41;
+    const float e32_b = -r32_b * c.r32 * c.r32, e42_b = -r42_bb * c.r42 * c.r42;
+    // x = E - E1, z = E - E2, q = E3 - E, p = E4 - E
+    Eb[0] = -x_b - e31_b - e41_b;
+    Eb[1] = -z_b - e32_b - e42_b;
+    Eb[2] = q_b + e31_b + e32_b;
+    Eb[3] = p_b + e41_b + e42_b;
+  } else {  // E3 < E < E4
+    const float y = c.e41 - x;
+    const float t = 4.0f * c.kC * y * y;
+    const float u = t * y;
+    g[0] = u * c.r41;
+    g[1] = u * c.r42;
+    g[2] = u * c.r43;
+    g[3] = t * (3.0f - y * c.sC);
+    float t_b = s[3] * (3.0f - y * c.sC);
+    float y_b = -s[3] * t * c.sC;
+    const float sC_b = -s[3] * t * y;
+    const float u_b = s[0] * c.r41 + s[1] * c.r42 + s[2] * c.r43;
+    float r41_b = s[0] * u, r42_b = s[1] * u, r43_b = s[2] * u;
+    t_b += u_b * y;
+    y_b += u_b * t;
+    const float kC_b = t_b * 4.0f * y * y;
+    y_b += t_b * 8.0f * c.kC * y;
+    r41_b += sC_b + kC_b * V * c.r42 * c.r43;
+    r42_b += sC_b + kC_b * V * c.r41 * c.r43;
+    r43_b += sC_b + kC_b * V * c.r41 * c.r42;
+    const float e41_b = -r41_b * c.r41 * c.r41, e42_b = -r42_b * c.r42 * c.r42, e43_b = -r43_b * c.r43 * c.r43;
+    Eb[0] = -e41_b;
+    Eb[1] = -e42_b;
+    Eb[2] = -e43_b;
+    Eb[3] = e41_b + e42_b + e43_b + y_b;
+  }
+}
+
+// Window of grid indices j with E1 < E_j < E4, clipped to [lo, hi]; empty when jlo > jhi.
+// Computed in FP32; a boundary index it gets wrong carries a weight that vanishes quadratically, and
+// the caller re-checks 0 < x < E41 per index.
+__device__ __forceinline__ void energy_window(float e1, float e4, float e0, float inv_de, int lo, int hi, int& jlo,
+                                              int& jhi) {
+  const float big = 3.0e7f;  // beyond any supported grid length (ne < 2^24)
+  float t1 = (e1 - e0) * inv_de;
+  float t4 = (e4 - e0) * inv_de;
+  t1 = fminf(fmaxf(t1, -2.0f), big);
+  t4 = fminf(fmaxf(t4, -2.0f), big);
+  jlo = max((int)floorf(t1) + 1, lo);
+  jhi = min((int)ceilf(t4) - 1, hi);
+}
+
+// Global float add without a compare-and-swap loop (device memory from hipMalloc).
+__device__ __forceinline__ void atomic_add_global(float* p, float v) { unsafeAtomicAdd(p, v); }
+
+}  // namespace tetra

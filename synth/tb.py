@@ -91,10 +91,13 @@ def band_structure(norb: int, seed: int, grid, cache: bool = True, workers: int 
         with ThreadPoolExecutor(workers) as ex:
             list(ex.map(run, bounds))
     if cache:
-        os.makedirs(os.path.dirname(path), exist_ok=True)
-        tmp = path + f".tmp{os.getpid()}.npz"
-        np.savez(tmp, eps=eps, w=w)
-        os.replace(tmp, path)
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            tmp = path + f".tmp{os.getpid()}.npz"
+            np.savez(tmp, eps=eps, w=w)
+            os.replace(tmp, path)
+        except OSError:
+            pass  # an unwritable cache only costs the next caller the diagonalisation
     return eps, w
 
 
@@ -108,7 +111,7 @@ def energy_grid(eps_list, ne: int, pad: float = 0.1):
         eps_list = [eps_list]
     lo = float(min(float(np.min(e)) for e in eps_list))
     hi = float(max(float(np.max(e)) for e in eps_list))
-    span = hi - lo
+    span = hi - lo if hi > lo else 1.0  # a single energy level still gets a usable grid
     e0 = float(np.float32(lo - pad * span))
     de = float(np.float32((hi + pad * span - e0) / max(ne - 1, 1)))
     return e0, de

@@ -1,0 +1,107 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every function declared in
+include/tetra.h, and rejects invalid arguments before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1710_10789_amd as tetra
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tetra.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tetra_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(tetra.library_path()):
+        from paper_1710_10789_amd import build
+
+        build.build()
+    return tetra.lib()
+
+
+def test_header_declares_the_entry_points():
+    names = _declared_functions()
+    for n in ("tetra_dos_forward", "tetra_dos_backward", "tetra_dos_batched", "tetra_dos_batched_workspace",
+              "tetra_status_string", "tetra_last_hip_error", "tetra_version"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    for name in _declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_status_strings(L):
+    assert L.tetra_status_string(0) == b"ok"
+    assert L.tetra_status_string(-1) == b"invalid argument"
+    assert L.tetra_status_string(-2) == b"unsupported request"
+    assert L.tetra_status_string(-3) == b"workspace missing or too small"
+    assert L.tetra_status_string(-4) == b"HIP runtime error"
+    assert L.tetra_status_string(123) == b"unknown status"
+    assert L.tetra_version() >= 100
+
+
+FAKE = 0x1000  # never dereferenced: validation fails before any launch
+
+
+def _fwd(L, d, eps=FAKE, w=FAKE, wtype=0, scale=None, dos=FAKE, flags=0):
+    return L.tetra_dos_forward(ctypes.byref(d) if d is not None else None, eps, w, wtype, scale, dos, flags, None)
+
+
+def _bwd(L, d, gd=FAKE, ge=FAKE, gw=FAKE, flags=0, wtype=0, scale=None):
+    return L.tetra_dos_backward(ctypes.byref(d), FAKE, FAKE, wtype, scale, gd, ge, gw, flags, None)
+
+
+def good():
+    return tetra.make_desc((4, 4, 4), 2, 3, -1.0, 0.01, 100)
+
+
+@pytest.mark.parametrize(
+    "field,value,status",
+    [
+        ("n1", 0, -1), ("n2", -3, -1), ("n3", 0, -1), ("nb", 0, -1), ("norb", 0, -1), ("ne", 0, -1),
+        ("de", 0.0, -1), ("de", -0.5, -1), ("de", float("nan"), -1), ("e0", float("inf"), -1),
+        ("e0", float("nan"), -1), ("norb", 17, -2), ("ne", 1 << 24, -1), ("n1", 1 << 28, -1),
+    ],
+)
+def test_forward_rejects_bad_descriptors(L, field, value, status):
+    d = good()
+    setattr(d, field, value)
+    assert _fwd(L, d) == status
+
+
+def test_forward_rejects_bad_pointers_and_flags(L):
+    assert _fwd(L, None) == -1
+    assert _fwd(L, good(), eps=None) == -1
+    assert _fwd(L, good(), w=None) == -1
+    assert _fwd(L, good(), dos=None) == -1
+    assert _fwd(L, good(), wtype=7) == -1
+    assert _fwd(L, good(), wtype=0, scale=FAKE) == -1  # FP32 weights take no scale
+    assert _fwd(L, good(), wtype=1, scale=None) == -1  # FP16 weights need a scale
+    assert _fwd(L, good(), flags=8) == -1
+    d = good()
+    d.e0, d.de, d.ne = 3.0e38, 1.0e37, 1000  # last grid energy overflows FP32
+    assert _fwd(L, d) == -1
+
+
+def test_backward_rejects_bad_arguments(L):
+    assert _bwd(L, good(), gd=None) == -1
+    assert _bwd(L, good(), ge=None, gw=None) == -1
+    d = good()
+    d.norb = 40
+    assert _bwd(L, d) == -2
+    assert _bwd(L, good(), flags=4) == -1
+
+
+def test_batched_rejects_bad_arguments(L):
+    assert L.tetra_dos_batched(None, 1, 0, 0, None, 0, None) == -1
+    items = (tetra.TetraItem * 1)()
+    assert L.tetra_dos_batched(items, 0, 0, 0, None, 0, None) == -1

@@ -217,3 +217,14 @@ def test_histogram_convergence_cosine_band(oracle_lib):
         errs.append(np.abs(binned - hist).sum() * width)
     assert errs[0] > errs[1] > errs[2]
     assert errs[2] < 0.02
+
+
+def test_bench_window_count_matches_oracle(oracle_lib):
+    """The benchmark's in-window update count (the unit of its roofline) equals the oracle's count."""
+    import bench
+
+    for grid, norb, ne in (((16, 16, 16), 8, 200), ((5, 3, 7), 3, 333)):
+        eps, w = synth.band_structure(norb, 1, grid)
+        e0, de = synth.energy_grid(eps, ne)
+        _, cnt = oracle_lib.dos(eps, w, grid, e0, de, ne)
+        assert bench.count_window_updates(eps, grid, e0, de, ne) == cnt
