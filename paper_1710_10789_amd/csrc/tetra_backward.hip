@@ -138,7 +138,7 @@ __global__ __launch_bounds__(NT) void dos_backward_kernel(BwdArgs a) {
     emax = fmaxf(emax, s_red[NT / 64 + i]);
   }
   int J0 = 0, J1 = -1;
-  if (emin <= emax) energy_window(emin, emax, a.e0, a.inv_de, 0, a.ne - 1, J0, J1);
+  if (emin <= emax) range_window(emin, emax, a.e0, a.inv_de, a.ne, J0, J1);
 
   const int ncubes = P1.cnt * P2.cnt * P3.cnt;
   auto point_offset = [](int s) { return (s & 1) * (SY * SZ) + ((s >> 1) & 1) * SZ + (s >> 2); };
@@ -165,12 +165,14 @@ __global__ __launch_bounds__(NT) void dos_backward_kernel(BwdArgs a) {
         sort4(e, s);
         int jlo, jhi;
         energy_window(e[0], e[3], a.e0, a.inv_de, c0, c1, jlo, jhi);
-        if (jlo > jhi) continue;
+        if (jlo > jhi + 2) continue;  // empty even after moving both ends by one
         int own[4];
 #pragma unroll
         for (int l = 0; l < 4; ++l) own[l] = s_own[pbase + point_offset(s[l])];
         if ((own[0] & own[1] & own[2] & own[3]) < 0) continue;  // no owned corner
         const TetSetup cs = tet_setup(e, a.e0, a.V);
+        tet_window(cs, a.de, c0, c1, jlo, jhi);
+        if (jlo > jhi) continue;
         float bb[4][NORB], gb[4][NORB];
         float ge[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll

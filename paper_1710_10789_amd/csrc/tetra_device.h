@@ -26,7 +26,7 @@ namespace tetra {
 //   {1,2,3,6} {2,3,4,6} {1,3,5,6} {3,4,6,8} {3,5,6,7} {3,6,7,8}
 // Returned as corner slots s = L - 1 in 4-bit fields (slot of the l-th corner at bits 4l..4l+2).
 // t is uniform across a wavefront, so the switch is a scalar branch.
-__device__ __forceinline__ uint32_t tet_slots(int t) {
+__host__ __device__ __forceinline__ uint32_t tet_slots(int t) {
   switch (t) {
     case 0: return 0x5210u;
     case 1: return 0x5321u;
@@ -37,12 +37,12 @@ __device__ __forceinline__ uint32_t tet_slots(int t) {
   }
 }
 
-__device__ __forceinline__ bool finite4(float a, float b, float c, float d) {
+__host__ __device__ __forceinline__ bool finite4(float a, float b, float c, float d) {
   return __builtin_isfinite(a) && __builtin_isfinite(b) && __builtin_isfinite(c) && __builtin_isfinite(d);
 }
 
 // Compare-exchange carrying an integer tag (corner slot) with the energy.
-__device__ __forceinline__ void cswap(float& ea, int& sa, float& eb, int& sb) {
+__host__ __device__ __forceinline__ void cswap(float& ea, int& sa, float& eb, int& sb) {
   const bool sw = eb < ea;
   const float lo = sw ? eb : ea;
   const float hi = sw ? ea : eb;
@@ -57,7 +57,7 @@ __device__ __forceinline__ void cswap(float& ea, int& sa, float& eb, int& sb) {
 // Five-comparator network: ascending energies e[0..3] with their slots. Equal energies may end in
 // either order; the weights of corners with equal energies are equal, so the result does not depend
 // on it.
-__device__ __forceinline__ void sort4(float e[4], int s[4]) {
+__host__ __device__ __forceinline__ void sort4(float e[4], int s[4]) {
   cswap(e[0], s[0], e[1], s[1]);
   cswap(e[2], s[2], e[3], s[3]);
   cswap(e[0], s[0], e[2], s[2]);
@@ -66,7 +66,7 @@ __device__ __forceinline__ void sort4(float e[4], int s[4]) {
 }
 
 // a + b = hi + lo exactly (Knuth's two-sum).
-__device__ __forceinline__ void two_sum(float a, float b, float& hi, float& lo) {
+__host__ __device__ __forceinline__ void two_sum(float a, float b, float& hi, float& lo) {
   hi = a + b;
   const float bb = hi - a;
   lo = (a - (hi - bb)) + (b - bb);
@@ -82,7 +82,7 @@ struct TetSetup {
   float k1, k2, k3;            // middle case: V/(E31 E41), V/(E31 E32 E41), V/(E32 E41 E42)
 };
 
-__device__ __forceinline__ TetSetup tet_setup(const float e[4], float e0, float V) {
+__host__ __device__ __forceinline__ TetSetup tet_setup(const float e[4], float e0, float V) {
   TetSetup c;
   two_sum(e0, -e[0], c.d_hi, c.d_lo);
   c.e21 = e[1] - e[0];
@@ -107,12 +107,12 @@ __device__ __forceinline__ TetSetup tet_setup(const float e[4], float e0, float 
 }
 
 // x = E_j - E1 for E_j = e0 + j*de.
-__device__ __forceinline__ float local_x(const TetSetup& c, int j, float de) {
+__host__ __device__ __forceinline__ float local_x(const TetSetup& c, int j, float de) {
   return __builtin_fmaf((float)j, de, c.d_hi) + c.d_lo;
 }
 
 // dw_l/dE at local energy x (0 < x < E41 assumed by the caller), sorted-corner order.
-__device__ __forceinline__ void corner_dos(const TetSetup& c, float x, float g[4]) {
+__host__ __device__ __forceinline__ void corner_dos(const TetSetup& c, float x, float g[4]) {
   if (x <= c.e21) {  // E1 < E <= E2
     const float t = 4.0f * c.kA * x * x;
     const float u = t * x;
@@ -145,7 +145,7 @@ __device__ __forceinline__ void corner_dos(const TetSetup& c, float x, float g[4
 // Corner weights g[4] (as corner_dos) and, for given multipliers s[4], the gradient
 // Eb[i] = d(sum_l s_l g_l)/dE_i with respect to the four sorted corner energies at fixed E, by reverse
 // accumulation through the same expressions as corner_dos.
-__device__ __forceinline__ void corner_dos_adjoint(const TetSetup& c, float V, float x, const float s[4], float g[4],
+__host__ __device__ __forceinline__ void corner_dos_adjoint(const TetSetup& c, float V, float x, const float s[4], float g[4],
                                                    float Eb[4]) {
   if (x <= c.e21) {  // E1 < E <= E2
     const float t = 4.0f * c.kA * x * x;
@@ -262,21 +262,37 @@ __device__ __forceinline__ void corner_dos_adjoint(const TetSetup& c, float V, f
   }
 }
 
-// Window of grid indices j with E1 < E_j < E4, clipped to [lo, hi]; empty when jlo > jhi.
-// Computed in FP32; a boundary index it gets wrong carries a weight that vanishes quadratically, and
-// the caller re-checks 0 < x < E41 per index.
-__device__ __forceinline__ void energy_window(float e1, float e4, float e0, float inv_de, int lo, int hi, int& jlo,
-                                              int& jhi) {
+// Estimate of the window of grid indices j with E1 < E_j < E4, clipped to [lo, hi] (empty when
+// jlo > jhi). Computed in FP32 from absolute energies, so either end can be off by one index; use
+// tet_window to make it exact for one tetrahedron-band.
+__host__ __device__ __forceinline__ void energy_window(float e1, float e4, float e0, float inv_de, int lo, int hi,
+                                                       int& jlo, int& jhi) {
   const float big = 3.0e7f;  // beyond any supported grid length (ne < 2^24)
   float t1 = (e1 - e0) * inv_de;
   float t4 = (e4 - e0) * inv_de;
   t1 = fminf(fmaxf(t1, -2.0f), big);
   t4 = fminf(fmaxf(t4, -2.0f), big);
-  jlo = max((int)floorf(t1) + 1, lo);
-  jhi = min((int)ceilf(t4) - 1, hi);
+  const int a = (int)floorf(t1) + 1, b = (int)ceilf(t4) - 1;
+  jlo = a > lo ? a : lo;
+  jhi = b < hi ? b : hi;
 }
 
-// Global float add without a compare-and-swap loop (device memory from hipMalloc).
-__device__ __forceinline__ void atomic_add_global(float* p, float v) { unsafeAtomicAdd(p, v); }
+// Exact window {j in [lo, hi] : 0 < x_j < E41} of one tetrahedron-band, from the estimate and the
+// accurate local-frame x. A boundary index matters for the gradient: the derivative of the corner
+// weights with respect to E1 (or E4) vanishes only linearly in x (or E4 - E_j), with a prefactor
+// 1/(E21 E31 E41) that is large for narrow tetrahedra.
+__host__ __device__ __forceinline__ void tet_window(const TetSetup& c, float de, int lo, int hi, int& jlo, int& jhi) {
+  if (jlo > lo && local_x(c, jlo - 1, de) > 0.0f) --jlo;
+  if (jhi < hi && local_x(c, jhi + 1, de) < c.e41) ++jhi;
+}
+
+// Estimate of the energy range of a set of grid points, one index wider on each side than
+// energy_window so that it contains every exact tetrahedron window of the set.
+__host__ __device__ __forceinline__ void range_window(float emin, float emax, float e0, float inv_de, int ne, int& J0,
+                                                      int& J1) {
+  energy_window(emin, emax, e0, inv_de, 0, ne - 1, J0, J1);
+  J0 = J0 > 0 ? J0 - 1 : 0;
+  J1 = J1 < ne - 1 ? J1 + 1 : ne - 1;
+}
 
 }  // namespace tetra

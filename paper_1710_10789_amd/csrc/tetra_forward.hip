@@ -42,6 +42,9 @@ struct FwdArgs {
   int ntiles, nunits, per_xcd;
 };
 
+// Global float add without a compare-and-swap loop (device memory from hipMalloc).
+__device__ __forceinline__ void atomic_add_global(float* p, float v) { unsafeAtomicAdd(p, v); }
+
 __device__ __forceinline__ int wrap(int v, int n) {
   if (v >= n) v -= n;
   if (v >= n) v %= n;
@@ -109,7 +112,7 @@ __global__ __launch_bounds__(NT) void dos_forward_kernel(FwdArgs a) {
   }
   if (!(emin <= emax)) return;  // no finite energy in this tile-band (uniform across the block)
   int J0, J1;
-  energy_window(emin, emax, a.e0, a.inv_de, 0, a.ne - 1, J0, J1);
+  range_window(emin, emax, a.e0, a.inv_de, a.ne, J0, J1);
 
   // This lane's cube; corner slot s sits at LDS point pbase + point_offset(s).
   const int cz = tid % TZ, cy = (tid / TZ) % TY, cx = tid / (TZ * TY);
@@ -138,8 +141,10 @@ __global__ __launch_bounds__(NT) void dos_forward_kernel(FwdArgs a) {
         sort4(e, s);
         int jlo, jhi;
         energy_window(e[0], e[3], a.e0, a.inv_de, c0, c1, jlo, jhi);
-        if (jlo > jhi) continue;
+        if (jlo > jhi + 2) continue;  // empty even after moving both ends by one
         const TetSetup cs = tet_setup(e, a.e0, a.V);
+        tet_window(cs, a.de, c0, c1, jlo, jhi);
+        if (jlo > jhi) continue;
         float bb[4][NORB];
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
