@@ -134,7 +134,74 @@ def cpu_baseline(eps, w, grid, e0, de, ne, mode, G, gpu_fn):
     }
 
 
+def _read_csv(path):
+    import csv
+
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def summarize_profiles(kt_dir, fetch_dir=None, write_dir=None, copy_fetch_dir=None, copy_write_dir=None,
+                       command="", out_json=None):
+    """Markdown summary of rocprofv3 output (kernel-trace stats, and HBM bytes from FETCH_SIZE /
+    WRITE_SIZE scaled by what the same counters read for a device copy of known size)."""
+    lines = ["| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
+    for r in _read_csv(glob.glob(os.path.join(kt_dir, "*kernel_stats.csv"))[0]):
+        lines.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} |")
+    traffic = {}
+    if fetch_dir and write_dir and copy_fetch_dir and copy_write_dir:
+        def per_kernel(d, counter):
+            acc = {}
+            for r in _read_csv(glob.glob(os.path.join(d, "*counter_collection.csv"))[0]):
+                if r["Counter_Name"] == counter:
+                    acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+            return {k: sum(v) / len(v) for k, v in acc.items()}
+
+        cf = per_kernel(copy_fetch_dir, "FETCH_SIZE")
+        cw = per_kernel(copy_write_dir, "WRITE_SIZE")
+        ck = [k for k in cf if "copyBuffer" in k or "copy" in k.lower()][0]
+        copy_bytes = 64 * 1024 * 1024 * 4
+        f_fetch = copy_bytes / (cf[ck] * 1024)
+        f_write = copy_bytes / (cw[ck] * 1024)
+        fe = per_kernel(fetch_dir, "FETCH_SIZE")
+        wr = per_kernel(write_dir, "WRITE_SIZE")
+        lines += ["", f"Copy calibration: a 256 MiB device copy reads FETCH_SIZE {cf[ck]:.0f} KiB "
+                      f"(factor {f_fetch:.3f}) and WRITE_SIZE {cw[ck]:.0f} KiB (factor {f_write:.3f}).", "",
+                  "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM read MB | HBM write MB |", "|---|---|---|---|---|"]
+        for k in fe:
+            if k not in wr:
+                continue
+            rd, wt = fe[k] * 1024 * f_fetch, wr[k] * 1024 * f_write
+            lines.append(f"| `{k[:90]}` | {fe[k]:.0f} | {wr[k]:.0f} | {rd / 1e6:.2f} | {wt / 1e6:.2f} |")
+            for short in ("dos_forward_kernel", "dos_backward_kernel"):
+                if short in k:
+                    traffic[short] = {"source_sha": kernel_source_hash(), "bytes_per_launch": rd + wt,
+                                      "read_bytes": rd, "write_bytes": wt}
+    if out_json and traffic:
+        with open(out_json, "w") as f:
+            json.dump(traffic, f, indent=1)
+    text = "\n".join(lines)
+    if command:
+        text = f"Command: `{command}`\n\n" + text
+    print(text)
+    return text
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-profiles":
+        ap = argparse.ArgumentParser()
+        ap.add_argument("--summarize-profiles", action="store_true")
+        ap.add_argument("--kt", required=True)
+        ap.add_argument("--fetch")
+        ap.add_argument("--write")
+        ap.add_argument("--copy-fetch")
+        ap.add_argument("--copy-write")
+        ap.add_argument("--command", default="")
+        ap.add_argument("--traffic-json")
+        a = ap.parse_args()
+        summarize_profiles(a.kt, a.fetch, a.write, a.copy_fetch, a.copy_write, a.command, a.traffic_json)
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)

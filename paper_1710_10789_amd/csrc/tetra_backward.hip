@@ -10,8 +10,12 @@
 //
 // Work decomposition: output-stationary. One workgroup owns a tile of OX x OY x OZ k-points of one
 // band and processes every cube that has one of them as a corner (the tile's cubes plus a one-cube
-// halo below it, recomputed by the neighbouring workgroups too). Gradients of owned points are summed
-// in LDS and written once with plain coalesced stores: no global atomics and no zero-fill pass.
+// halo below it, recomputed by the neighbouring workgroups too). Gradients of owned points are
+// written once with plain coalesced stores: no global atomics and no zero-fill pass.
+// Inside the workgroup there are no atomics either (LDS float atomics are slow on gfx950): all lanes
+// work on the same tetrahedron index t at a time, one cube per lane, so for each of t's four corners
+// the map cube -> corner point is injective across lanes. After a tetrahedron, four barrier-separated
+// rounds add each lane's per-corner sums into LDS point totals with plain read-modify-writes.
 
 #include "tetra_device.h"
 #include "tetra_internal.h"
@@ -79,9 +83,8 @@ __global__ __launch_bounds__(NT) void dos_backward_kernel(BwdArgs a) {
   constexpr int LC = HCAP / NORB;
   __shared__ float s_eps[NSP];
   __shared__ float s_w[NSP * NORB];
-  __shared__ short s_own[NSP];  // owned-point index of a staged point, or -1
-  __shared__ float s_ge[NOWN];
-  __shared__ float s_gw[NOWN * NORB];
+  __shared__ short s_own[NSP];     // owned-point index of a staged point, or -1
+  __shared__ float s_pt[NSP * (NORB + 1)];  // per staged point: dL/deps, then dL/db[0..NORB)
   __shared__ float s_G[HCAP];
   __shared__ float s_red[2 * (NT / 64)];
 
@@ -98,8 +101,7 @@ __global__ __launch_bounds__(NT) void dos_backward_kernel(BwdArgs a) {
   const float* eps_n = a.eps + (int64_t)band * nk;
   const float* w_n = a.w + (int64_t)band * NORB * nk;
 
-  for (int q = tid; q < NOWN; q += NT) s_ge[q] = 0.0f;
-  for (int q = tid; q < NOWN * NORB; q += NT) s_gw[q] = 0.0f;
+  for (int q = tid; q < NSP * (NORB + 1); q += NT) s_pt[q] = 0.0f;
 
   // Stage the corner points of the processed cubes; mark the owned ones.
   float lmin = __builtin_huge_valf(), lmax = -__builtin_huge_valf();
@@ -148,8 +150,11 @@ __global__ __launch_bounds__(NT) void dos_backward_kernel(BwdArgs a) {
     const int L = c1 - c0 + 1;
     for (int q = tid; q < L * NORB; q += NT) s_G[q] = a.G[(int64_t)c0 * NORB + q];
     __syncthreads();
-    for (int c = tid; c < ncubes; c += NT) {
-      const int c3 = c % P3.cnt, c2 = (c / P3.cnt) % P2.cnt, c1i = c / (P3.cnt * P2.cnt);
+    for (int cr = 0; cr < ncubes; cr += NT) {  // rounds of one cube per lane
+      const int c = cr + tid;
+      const bool active = c < ncubes;
+      const int c3 = active ? c % P3.cnt : 0, c2 = active ? (c / P3.cnt) % P2.cnt : 0;
+      const int c1i = active ? c / (P3.cnt * P2.cnt) : 0;
       const int pbase = (c1i * SY + c2) * SZ + c3;
 #pragma unroll 1
       for (int t = 0; t < 6; ++t) {
@@ -161,74 +166,112 @@ __global__ __launch_bounds__(NT) void dos_backward_kernel(BwdArgs a) {
           s[l] = (slots >> (4 * l)) & 7;
           e[l] = s_eps[pbase + point_offset(s[l])];
         }
-        if (!finite4(e[0], e[1], e[2], e[3])) continue;
-        sort4(e, s);
-        int jlo, jhi;
-        energy_window(e[0], e[3], a.e0, a.inv_de, c0, c1, jlo, jhi);
-        if (jlo > jhi + 2) continue;  // empty even after moving both ends by one
-        int own[4];
-#pragma unroll
-        for (int l = 0; l < 4; ++l) own[l] = s_own[pbase + point_offset(s[l])];
-        if ((own[0] & own[1] & own[2] & own[3]) < 0) continue;  // no owned corner
-        const TetSetup cs = tet_setup(e, a.e0, a.V);
-        tet_window(cs, a.de, c0, c1, jlo, jhi);
-        if (jlo > jhi) continue;
-        float bb[4][NORB], gb[4][NORB];
+        float gb[4][NORB];
         float ge[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int l = 0; l < 4; ++l) {
-          const int p = pbase + point_offset(s[l]);
+        for (int l = 0; l < 4; ++l)
 #pragma unroll
-          for (int m = 0; m < NORB; ++m) {
-            bb[l][m] = s_w[p * NORB + m];
-            gb[l][m] = 0.0f;
+          for (int m = 0; m < NORB; ++m) gb[l][m] = 0.0f;
+        bool any = false;  // this lane has something to add for tetrahedron t
+        if (active && finite4(e[0], e[1], e[2], e[3])) {
+          sort4(e, s);
+          int jlo, jhi;
+          energy_window(e[0], e[3], a.e0, a.inv_de, c0, c1, jlo, jhi);
+          bool owned_corner = false;
+#pragma unroll
+          for (int l = 0; l < 4; ++l) owned_corner = owned_corner || (s_own[pbase + point_offset(s[l])] >= 0);
+          if (jlo <= jhi + 2 && owned_corner) {
+            const TetSetup cs = tet_setup(e, a.e0, a.V);
+            tet_window(cs, a.de, c0, c1, jlo, jhi);
+            if (jlo <= jhi) {
+              any = true;
+              float bb[4][NORB];
+#pragma unroll
+              for (int l = 0; l < 4; ++l) {
+                const int p = pbase + point_offset(s[l]);
+#pragma unroll
+                for (int m = 0; m < NORB; ++m) bb[l][m] = s_w[p * NORB + m];
+              }
+              for (int j = jlo; j <= jhi; ++j) {
+                const float x = local_x(cs, j, a.de);
+                if (!(x > 0.0f && x < cs.e41)) continue;
+                const float* Gj = &s_G[(j - c0) * NORB];
+                float Gm[NORB];
+#pragma unroll
+                for (int m = 0; m < NORB; ++m) Gm[m] = Gj[m];
+                float sl[4];
+#pragma unroll
+                for (int l = 0; l < 4; ++l) {
+                  float acc = 0.0f;
+#pragma unroll
+                  for (int m = 0; m < NORB; ++m) acc += Gm[m] * bb[l][m];
+                  sl[l] = acc;
+                }
+                float g[4], Eb[4];
+                corner_dos_adjoint(cs, a.V, x, sl, g, Eb);
+#pragma unroll
+                for (int l = 0; l < 4; ++l) {
+                  ge[l] += Eb[l];
+#pragma unroll
+                  for (int m = 0; m < NORB; ++m) gb[l][m] += Gm[m] * g[l];
+                }
+              }
+            }
           }
         }
-        for (int j = jlo; j <= jhi; ++j) {
-          const float x = local_x(cs, j, a.de);
-          if (!(x > 0.0f && x < cs.e41)) continue;
-          const float* Gj = &s_G[(j - c0) * NORB];
-          float Gm[NORB];
+        // Four rounds, one per static corner of tetrahedron t: for a fixed corner slot the target
+        // points of different lanes are distinct, so plain read-modify-writes do not race.
 #pragma unroll
-          for (int m = 0; m < NORB; ++m) Gm[m] = Gj[m];
-          float sl[4];
+        for (int q = 0; q < 4; ++q) {
+          const int slot = (slots >> (4 * q)) & 7;
+          // sorted position of this corner
+          const int i = (s[0] == slot) ? 0 : (s[1] == slot) ? 1 : (s[2] == slot) ? 2 : 3;
+          __syncthreads();
+          if (any) {
+            float* dst = &s_pt[(pbase + point_offset(slot)) * (NORB + 1)];
+            float v = (i == 0) ? ge[0] : (i == 1) ? ge[1] : (i == 2) ? ge[2] : ge[3];
+            dst[0] += v;
 #pragma unroll
-          for (int l = 0; l < 4; ++l) {
-            float acc = 0.0f;
-#pragma unroll
-            for (int m = 0; m < NORB; ++m) acc += Gm[m] * bb[l][m];
-            sl[l] = acc;
+            for (int m = 0; m < NORB; ++m) {
+              v = (i == 0) ? gb[0][m] : (i == 1) ? gb[1][m] : (i == 2) ? gb[2][m] : gb[3][m];
+              dst[1 + m] += v;
+            }
           }
-          float g[4], Eb[4];
-          corner_dos_adjoint(cs, a.V, x, sl, g, Eb);
-#pragma unroll
-          for (int l = 0; l < 4; ++l) {
-            ge[l] += Eb[l];
-#pragma unroll
-            for (int m = 0; m < NORB; ++m) gb[l][m] += Gm[m] * g[l];
-          }
-        }
-#pragma unroll
-        for (int l = 0; l < 4; ++l) {
-          if (own[l] < 0) continue;
-          atomicAdd(&s_ge[own[l]], ge[l]);
-#pragma unroll
-          for (int m = 0; m < NORB; ++m) atomicAdd(&s_gw[own[l] * NORB + m], gb[l][m]);
         }
       }
     }
     __syncthreads();
   }
 
-  // Write the owned points (coalesced along axis 3).
+  // Write the owned points (coalesced along axis 3). With periodic wrap on a short axis one k-point
+  // can appear at several staged positions; their partial sums are added here.
   for (int q = tid; q < NOWN; q += NT) {
     const int d3 = q % OZ, d2 = (q / OZ) % OY, d1 = q / (OZ * OY);
     if (d1 >= P1.own || d2 >= P2.own || d3 >= P3.own) continue;
+    float ge = 0.0f;
+    float gw[NORB];
+#pragma unroll
+    for (int m = 0; m < NORB; ++m) gw[m] = 0.0f;
+    // staged copies of owned point (x0+d1, y0+d2, z0+d3): local index i_a with (start_a + i_a) % n_a
+    // equal to its coordinate, i_a in [0, cnt_a]
+    for (int i1 = 0; i1 <= P1.cnt; ++i1) {
+      if (wrap_pos(P1.start + i1, a.n1) != P1.x0 + d1) continue;
+      for (int i2 = 0; i2 <= P2.cnt; ++i2) {
+        if (wrap_pos(P2.start + i2, a.n2) != P2.x0 + d2) continue;
+        for (int i3 = 0; i3 <= P3.cnt; ++i3) {
+          if (wrap_pos(P3.start + i3, a.n3) != P3.x0 + d3) continue;
+          const float* src = &s_pt[((i1 * SY + i2) * SZ + i3) * (NORB + 1)];
+          ge += src[0];
+#pragma unroll
+          for (int m = 0; m < NORB; ++m) gw[m] += src[1 + m];
+        }
+      }
+    }
     const int64_t k = ((int64_t)(P1.x0 + d1) * a.n2 + (P2.x0 + d2)) * a.n3 + (P3.x0 + d3);
-    if (a.grad_eps) a.grad_eps[(int64_t)band * nk + k] = s_ge[q];
+    if (a.grad_eps) a.grad_eps[(int64_t)band * nk + k] = ge;
     if (a.grad_w) {
 #pragma unroll
-      for (int m = 0; m < NORB; ++m) a.grad_w[((int64_t)band * NORB + m) * nk + k] = s_gw[q * NORB + m];
+      for (int m = 0; m < NORB; ++m) a.grad_w[((int64_t)band * NORB + m) * nk + k] = gw[m];
     }
   }
 }

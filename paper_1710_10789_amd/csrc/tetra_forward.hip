@@ -14,6 +14,14 @@
 //  * per (tetrahedron, band, energy): the four corner weights (tetra_device.h) contracted with the
 //    four corners' orbital weights, added to an LDS histogram that covers only the tile-band's
 //    energy range;
+//  * the LDS histogram holds 64-bit fixed-point integers: LDS float atomics are an order of
+//    magnitude slower than integer ones on gfx950. Every contribution is non-negative (a corner
+//    weight is the section integral of a barycentric coordinate) and a tetrahedron's point DOS never
+//    exceeds 3 V_T/(V_G E41), so with bmax = max |b| of the tile, a per-workgroup bound
+//    B = sum 12 V bmax / E41 over the tetrahedra with a non-empty window bounds every bin's |sum| and
+//    fixes a power-of-two scale S with B*S <= 2^62 (two's complement, so signed weights work too).
+//    The in-LDS sum is then exact and independent of the order of the atomics; the only rounding
+//    left is that of each FP32 contribution;
 //  * one global float atomic per touched (energy, orbital) bin when the workgroup finishes.
 // Workgroups are assigned so that each XCD (eight per MI355X, each with its own L2) works through a
 // contiguous range of tiles of the same band, keeping shared halo points in one L2.
@@ -29,7 +37,7 @@ constexpr int TX = 4, TY = 4, TZ = 16;  // cubes per tile along grid axes 1, 2, 
 constexpr int NT = TX * TY * TZ;        // one lane per cube
 constexpr int PX = TX + 1, PY = TY + 1, PZ = TZ + 1;
 constexpr int NP = PX * PY * PZ;  // staged grid points (cube corners of the tile)
-constexpr int HCAP = 4096;        // LDS histogram capacity in floats
+constexpr int HCAP = 2048;        // LDS histogram capacity in 64-bit words
 constexpr int NXCD = 8;
 
 struct FwdArgs {
@@ -59,14 +67,18 @@ __device__ __forceinline__ float wave_max(float v) {
   for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
   return v;
 }
+__device__ __forceinline__ float wave_sum(float v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
 
 template <int NORB>
 __global__ __launch_bounds__(NT) void dos_forward_kernel(FwdArgs a) {
   constexpr int LC = ((HCAP / NORB) - 1) & ~1;  // energies per histogram pass (even)
   __shared__ float s_eps[NP];
   __shared__ float s_w[NP * NORB];
-  __shared__ float s_hist[HCAP];
-  __shared__ float s_red[2 * (NT / 64)];
+  __shared__ unsigned long long s_hist[HCAP];
+  __shared__ float s_red[3 * (NT / 64)];
 
   // XCD-aware mapping: hardware dispatches block b to XCD b % 8; give each XCD a contiguous range.
   const int b = blockIdx.x;
@@ -84,7 +96,7 @@ __global__ __launch_bounds__(NT) void dos_forward_kernel(FwdArgs a) {
   const float* w_n = a.w + (int64_t)band * NORB * nk;
 
   // Stage the tile's grid points (periodic wrap) and find their energy range.
-  float lmin = __builtin_huge_valf(), lmax = -__builtin_huge_valf();
+  float lmin = __builtin_huge_valf(), lmax = -__builtin_huge_valf(), lbmax = 0.0f;
   for (int p = tid; p < NP; p += NT) {
     const int pz = p % PZ, py = (p / PZ) % PY, px = p / (PZ * PY);
     const int64_t k = ((int64_t)wrap(x0 + px, a.n1) * a.n2 + wrap(y0 + py, a.n2)) * a.n3 + wrap(z0 + pz, a.n3);
@@ -95,20 +107,27 @@ __global__ __launch_bounds__(NT) void dos_forward_kernel(FwdArgs a) {
       lmax = fmaxf(lmax, e);
     }
 #pragma unroll
-    for (int m = 0; m < NORB; ++m) s_w[p * NORB + m] = w_n[(int64_t)m * nk + k];
+    for (int m = 0; m < NORB; ++m) {
+      const float b = w_n[(int64_t)m * nk + k];
+      s_w[p * NORB + m] = b;
+      lbmax = fmaxf(lbmax, fabsf(b));
+    }
   }
   lmin = wave_min(lmin);
   lmax = wave_max(lmax);
+  lbmax = wave_max(lbmax);
   if ((tid & 63) == 0) {
     s_red[tid >> 6] = lmin;
     s_red[(NT / 64) + (tid >> 6)] = lmax;
+    s_red[2 * (NT / 64) + (tid >> 6)] = lbmax;
   }
   __syncthreads();
-  float emin = s_red[0], emax = s_red[NT / 64];
+  float emin = s_red[0], emax = s_red[NT / 64], bmax = s_red[2 * (NT / 64)];
 #pragma unroll
   for (int i = 1; i < NT / 64; ++i) {
     emin = fminf(emin, s_red[i]);
     emax = fmaxf(emax, s_red[NT / 64 + i]);
+    bmax = fmaxf(bmax, s_red[2 * (NT / 64) + i]);
   }
   if (!(emin <= emax)) return;  // no finite energy in this tile-band (uniform across the block)
   int J0, J1;
@@ -120,11 +139,47 @@ __global__ __launch_bounds__(NT) void dos_forward_kernel(FwdArgs a) {
   const int pbase = (cx * PY + cy) * PZ + cz;
   auto point_offset = [](int s) { return (s & 1) * (PY * PZ) + ((s >> 1) & 1) * PZ + (s >> 2); };
 
+  // Bound on any bin's sum: sum over tetrahedra with a possibly non-empty window of 12 V bmax / E41.
+  float bound = 0.0f;
+  if (valid) {
+#pragma unroll 1
+    for (int t = 0; t < 6; ++t) {
+      const uint32_t slots = tet_slots(t);
+      float lo = __builtin_huge_valf(), hi = -__builtin_huge_valf();
+      bool fin = true;
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        const float e = s_eps[pbase + point_offset((slots >> (4 * l)) & 7)];
+        fin = fin && __builtin_isfinite(e);
+        lo = fminf(lo, e);
+        hi = fmaxf(hi, e);
+      }
+      if (!fin || !(hi > lo)) continue;
+      int jlo, jhi;
+      energy_window(lo, hi, a.e0, a.inv_de, J0, J1, jlo, jhi);
+      if (jlo > jhi + 2) continue;
+      bound += 12.0f * a.V * bmax / (hi - lo);
+    }
+  }
+  bound = wave_sum(fminf(bound, 1.0e37f));
+  __syncthreads();  // every lane has read s_red
+  if ((tid & 63) == 0) s_red[tid >> 6] = bound;
+  __syncthreads();
+  float B = 0.0f;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) B += s_red[i];
+  if (!(B > 0.0f)) return;  // nothing to add (uniform across the block)
+  int bexp;
+  frexpf(fminf(B, 3.0e38f), &bexp);  // B <= 2^bexp
+  const int sexp = min(62 - bexp, 126);
+  const float S = ldexpf(1.0f, sexp);        // B * S <= 2^62
+  const double inv_S = ldexp(1.0, -sexp);
+
   for (int c0 = J0; c0 <= J1; c0 += LC) {
     const int c1 = min(c0 + LC - 1, J1);
     const int L = c1 - c0 + 1;
     const int LP = L | 1;  // odd row pitch: the flush reads across orbitals without bank conflicts
-    for (int q = tid; q < NORB * LP; q += NT) s_hist[q] = 0.0f;
+    for (int q = tid; q < NORB * LP; q += NT) s_hist[q] = 0ull;
     __syncthreads();
     if (valid) {
 #pragma unroll 1
@@ -157,11 +212,11 @@ __global__ __launch_bounds__(NT) void dos_forward_kernel(FwdArgs a) {
           if (!(x > 0.0f && x < cs.e41)) continue;
           float g[4];
           corner_dos(cs, x, g);
-          float* h = &s_hist[j - c0];
+          unsigned long long* h = &s_hist[j - c0];
 #pragma unroll
           for (int m = 0; m < NORB; ++m) {
             const float v = g[0] * bb[0][m] + g[1] * bb[1][m] + g[2] * bb[2][m] + g[3] * bb[3][m];
-            atomicAdd(&h[m * LP], v);
+            atomicAdd(&h[m * LP], (unsigned long long)__float2ll_rn(v * S));
           }
         }
       }
@@ -169,8 +224,8 @@ __global__ __launch_bounds__(NT) void dos_forward_kernel(FwdArgs a) {
     __syncthreads();
     for (int q = tid; q < L * NORB; q += NT) {
       const int r = q / NORB, m = q - r * NORB;
-      const float v = s_hist[m * LP + r];
-      if (v != 0.0f) atomic_add_global(&a.dos[(int64_t)(c0 + r) * NORB + m], v);
+      const unsigned long long qv = s_hist[m * LP + r];
+      if (qv != 0ull) atomic_add_global(&a.dos[(int64_t)(c0 + r) * NORB + m], (float)((double)(long long)qv * inv_S));
     }
     __syncthreads();
   }
