@@ -38,11 +38,18 @@ WORKLOAD = "k64_b8_e1000"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
-def kernel_source_hash() -> str:
+KERNEL_SOURCES = {
+    "dos_forward_kernel": ("tetra_forward.hip", "tetra_device.h", "tetra_internal.h"),
+    "dos_backward_kernel": ("tetra_backward.hip", "tetra_device.h", "tetra_internal.h"),
+}
+
+
+def kernel_source_hash(kernel: str) -> str:
+    """Hash of the sources a kernel is built from; a traffic record is used only while it matches."""
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1710_10789_amd", "csrc", "*"))):
-        with open(p, "rb") as f:
-            h.update(os.path.basename(p).encode())
+    for name in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_1710_10789_amd", "csrc", name), "rb") as f:
+            h.update(name.encode())
             h.update(f.read())
     return h.hexdigest()[:16]
 
@@ -98,7 +105,7 @@ def load_traffic(kernel):
             rec = json.load(f).get(kernel)
     except (OSError, ValueError):
         return None
-    if not rec or rec.get("source_sha") != kernel_source_hash():
+    if not rec or rec.get("source_sha") != kernel_source_hash(kernel):
         return None
     return rec.get("bytes_per_launch")
 
@@ -142,7 +149,7 @@ def _read_csv(path):
 
 
 def summarize_profiles(kt_dir, fetch_dir=None, write_dir=None, copy_fetch_dir=None, copy_write_dir=None,
-                       command="", out_json=None):
+                       command="", out_json=None, source_shas=None):
     """Markdown summary of rocprofv3 output (kernel-trace stats, and HBM bytes from FETCH_SIZE /
     WRITE_SIZE scaled by what the same counters read for a device copy of known size)."""
     lines = ["| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
@@ -176,7 +183,8 @@ def summarize_profiles(kt_dir, fetch_dir=None, write_dir=None, copy_fetch_dir=No
             lines.append(f"| `{k[:90]}` | {fe[k]:.0f} | {wr[k]:.0f} | {rd / 1e6:.2f} | {wt / 1e6:.2f} |")
             for short in ("dos_forward_kernel", "dos_backward_kernel"):
                 if short in k:
-                    traffic[short] = {"source_sha": kernel_source_hash(), "bytes_per_launch": rd + wt,
+                    sha = (source_shas or {}).get(short) or kernel_source_hash(short)
+                    traffic[short] = {"source_sha": sha, "bytes_per_launch": rd + wt,
                                       "read_bytes": rd, "write_bytes": wt}
     if out_json and traffic:
         with open(out_json, "w") as f:
@@ -199,8 +207,13 @@ def main():
         ap.add_argument("--copy-write")
         ap.add_argument("--command", default="")
         ap.add_argument("--traffic-json")
+        ap.add_argument("--bench-json", help="bench output of the profiled tree (its kernel source hashes)")
         a = ap.parse_args()
-        summarize_profiles(a.kt, a.fetch, a.write, a.copy_fetch, a.copy_write, a.command, a.traffic_json)
+        shas = None
+        if a.bench_json:
+            with open(a.bench_json) as f:
+                shas = json.loads(f.read().strip().splitlines()[-1]).get("kernel_source_sha")
+        summarize_profiles(a.kt, a.fetch, a.write, a.copy_fetch, a.copy_write, a.command, a.traffic_json, shas)
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -332,7 +345,7 @@ def main():
                          "hbm_gbs_algorithmic": b_fwd / t_fwd / 1e9},
         "roofline_bwd": ({"achieved": f_bwd / t_bwd / 1e12, "frac": f_bwd / t_bwd / 1e12 / PEAK_FP32_VALU_TFLOPS,
                           "hbm_gbs_algorithmic": b_bwd / t_bwd / 1e9} if use_bwd else None),
-        "kernel_source_sha": kernel_source_hash(),
+        "kernel_source_sha": {k: kernel_source_hash(k) for k in KERNEL_SOURCES},
     }
     if not args.no_cpu_baseline:
         def gpu_fn():

@@ -34,7 +34,7 @@
  *    is available from tetra_last_hip_error()).
  *  - Layouts are structure-of-arrays: eps[nb][nk], w[nb][norb][nk], dos[ne][norb].
  *  - Limits: norb in 1..16 (the paper's largest realistic model, Sec. III.B); n1,n2,n3,nb,ne >= 1;
- *    nb*nk < 2^31 and nb*norb*nk < 2^31; ne < 2^24; finite e0; finite de > 0.
+ *    nb*nk < 2^31 and nb*norb*nk < 2^31; ne <= 2^22; finite e0; finite de > 0.
  */
 #ifndef TETRA_H
 #define TETRA_H
@@ -61,7 +61,14 @@ typedef enum {
 
 /* Flag bits. */
 enum {
-  TETRA_KAHAN = 1u /* compensated (Kahan) FP32 accumulation of the per-workgroup histograms */
+  /* Compensated accumulation. Workgroup histograms are always summed exactly (64-bit fixed point
+   * in LDS); with this flag the cross-workgroup sum is exact as well (a bound pre-pass fixes one
+   * common scale, partial sums are added as 64-bit integers), so the only rounding left is that of
+   * each FP32 contribution and the result is bitwise reproducible. tetra_dos_forward then uses a
+   * library-owned device buffer of 256 + 8*ne*norb bytes, allocated on the first such call on a
+   * device and kept until the process ends; such calls must not overlap on one device. The adjoint
+   * sums at most eight partial values per output element and ignores the flag. */
+  TETRA_KAHAN = 1u
 };
 
 /* Problem descriptor (host memory). */
@@ -83,7 +90,7 @@ typedef struct {
  *   dos      device, float [ne][norb]      result, overwritten
  *   flags    0 or TETRA_KAHAN
  *   stream   hipStream_t
- * Allocates nothing.
+ * Allocates nothing, except the TETRA_KAHAN buffer described above.
  */
 tetra_status tetra_dos_forward(const tetra_desc* d, const float* eps, const void* w, int wtype,
                                const float* w_scale, float* dos, unsigned flags, void* stream);
@@ -113,17 +120,21 @@ typedef struct {
 } tetra_item;
 
 /*
- * Bytes of device workspace tetra_dos_batched needs for these items (host array of n items).
- * Returns 0 for invalid input.
+ * Bytes of device workspace tetra_dos_batched needs for these items (host array of n items):
+ * 256 per persistent launch. Returns 0 for invalid input.
  */
 size_t tetra_dos_batched_workspace(const tetra_item* items, int n, int wtype, unsigned flags);
 
 /*
- * Many independent problems (uneven grids, energy grids, band and orbital counts) in one
- * persistent launch over a flattened work queue. `items` is host memory; `workspace` is device
- * memory of at least tetra_dos_batched_workspace() bytes, owned by the caller and not used by
- * anything else until the work on `stream` completes. Each item's dos is overwritten.
- * Allocates nothing; the queue is written into the workspace with one host-to-device copy.
+ * Many independent problems (uneven grids, energy grids, band counts) through one persistent launch
+ * per group of up to 32 items with the same orbital count: workgroups pull (item, band, tile) units
+ * from a work counter, so problems of very different sizes share the chip. `items` is host memory
+ * read during the call (the descriptors travel as kernel arguments); `workspace` is device memory of
+ * at least tetra_dos_batched_workspace() bytes (one 256-byte counter per launch), owned by the caller
+ * and not used by anything else until the work on `stream` completes. Each item's dos is
+ * overwritten. Every item uses weight type wtype (with its own w_scale for TETRA_W_F16).
+ * Allocates nothing and copies nothing to the device, so a call can be captured in a HIP graph.
+ * flags must be 0 (TETRA_KAHAN is not supported here: TETRA_ERR_UNSUPPORTED).
  */
 tetra_status tetra_dos_batched(const tetra_item* items, int n, int wtype, unsigned flags,
                                void* workspace, size_t ws_bytes, void* stream);

@@ -24,6 +24,8 @@ __all__ = [
     "dos_forward",
     "dos_backward",
     "dos",
+    "dos_batched",
+    "batched_workspace_bytes",
     "from_eigh",
     "half_weights",
 ]
@@ -216,6 +218,69 @@ def dos_backward(eps, w, grid, e0, de, grad_dos, *, w_scale=None, need_eps=True,
         grad_w.data_ptr() if grad_w is not None else None, 0, _stream_handle(dev))
     _check("tetra_dos_backward", st)
     return grad_eps, grad_w
+
+
+def _batch_items(problems, out):
+    torch = _torch()
+    n = len(problems)
+    items = (TetraItem * n)()
+    outs = []
+    wtype = None
+    for i, pr in enumerate(problems):
+        eps, w, grid, e0, de, ne = pr[:6]
+        w_scale = pr[6] if len(pr) > 6 else None
+        nk, nb, norb = _shapes(eps, w, grid)
+        dev = eps.device
+        _require(eps, f"items[{i}].eps", (nb, nk), (torch.float32,), dev)
+        _require(w, f"items[{i}].w", (nb, norb, nk), (torch.float32, torch.float16), dev)
+        wt = TETRA_W_F16 if w.dtype == torch.float16 else TETRA_W_F32
+        if wtype is None:
+            wtype = wt
+        elif wt != wtype:
+            raise TypeError("all items of a batch need the same weight dtype")
+        if wt == TETRA_W_F16:
+            _require(w_scale, f"items[{i}].w_scale", (nb,), (torch.float32,), dev)
+        o = out[i] if out is not None else torch.empty((int(ne), norb), dtype=torch.float32, device=dev)
+        _require(o, f"out[{i}]", (int(ne), norb), (torch.float32,), dev)
+        outs.append(o)
+        items[i].d = make_desc(grid, nb, norb, e0, de, ne)
+        items[i].eps = eps.data_ptr()
+        items[i].w = w.data_ptr()
+        items[i].w_scale = w_scale.data_ptr() if w_scale is not None else None
+        items[i].dos = o.data_ptr()
+    return items, outs, wtype
+
+
+def batched_workspace_bytes(problems) -> int:
+    """Device workspace ``dos_batched`` needs for these problems (see ``tetra_dos_batched_workspace``)."""
+    items, _, wtype = _batch_items(problems, None)
+    return int(lib().tetra_dos_batched_workspace(items, len(problems), wtype, 0))
+
+
+def dos_batched(problems, *, workspace=None, out=None):
+    """DOS of many independent problems in one persistent launch per orbital count.
+
+    problems: sequence of ``(eps, w, grid, e0, de, ne)`` or ``(eps, w, grid, e0, de, ne, w_scale)``
+    with the same meaning as in :func:`dos_forward`. ``workspace`` is an optional uint8 device tensor
+    of at least :func:`batched_workspace_bytes` bytes (allocated here when omitted). Returns the list
+    of ``[ne, norb]`` results (``out`` if given).
+    """
+    torch = _torch()
+    if len(problems) == 0:
+        return []
+    items, outs, wtype = _batch_items(problems, out)
+    dev = problems[0][0].device
+    need = int(lib().tetra_dos_batched_workspace(items, len(problems), wtype, 0))
+    if need == 0:
+        raise TetraError("tetra_dos_batched_workspace", -1)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    if workspace.numel() < need or not workspace.is_cuda:
+        raise ValueError(f"workspace must be a device tensor of at least {need} bytes")
+    st = lib().tetra_dos_batched(items, len(problems), wtype, 0, workspace.data_ptr(), workspace.numel(),
+                                 _stream_handle(dev))
+    _check("tetra_dos_batched", st)
+    return outs
 
 
 def _autograd_function():

@@ -2,6 +2,8 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <vector>
 
 #include "tetra_internal.h"
 
@@ -16,12 +18,45 @@ tetra_status hip_status(hipError_t e) {
   return TETRA_ERR_HIP;
 }
 
+// Library-owned scratch for the exact (TETRA_KAHAN) forward: one buffer per device, allocated on first
+// use and grown when a larger problem needs it; kept until the process ends. Calls with TETRA_KAHAN
+// that overlap on one device race on it.
+struct DeviceScratch {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+std::mutex g_scratch_mu;
+std::vector<DeviceScratch> g_scratch;
+
+hipError_t exact_scratch(size_t bytes, void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch.size() <= dev) g_scratch.resize(dev + 1);
+  DeviceScratch& s = g_scratch[dev];
+  if (s.bytes < bytes) {
+    if (s.ptr) {
+      e = hipFree(s.ptr);  // waits for work that may still use it
+      if (e != hipSuccess) return e;
+      s.ptr = nullptr;
+      s.bytes = 0;
+    }
+    const size_t want = bytes < (1u << 20) ? (1u << 20) : bytes;
+    e = hipMalloc(&s.ptr, want);
+    if (e != hipSuccess) return e;
+    s.bytes = want;
+  }
+  *out = s.ptr;
+  return hipSuccess;
+}
+
 // Shape and range checks shared by every entry point (no HIP call).
 tetra_status check_desc(const tetra_desc* d) {
   if (!d) return TETRA_ERR_ARG;
   if (d->n1 < 1 || d->n2 < 1 || d->n3 < 1 || d->nb < 1 || d->norb < 1 || d->ne < 1) return TETRA_ERR_ARG;
   if (!std::isfinite(d->e0) || !std::isfinite(d->de) || !(d->de > 0.0f)) return TETRA_ERR_ARG;
-  if (d->ne >= (1 << 24)) return TETRA_ERR_ARG;
+  if (d->ne > (1 << 22)) return TETRA_ERR_ARG;  // keeps FP32 window estimates within one index
   const double nk = (double)d->n1 * d->n2 * d->n3;
   if (nk * d->nb >= 2147483648.0 || nk * d->nb * d->norb >= 2147483648.0) return TETRA_ERR_ARG;
   if ((double)d->ne * d->norb >= 2147483648.0) return TETRA_ERR_ARG;
@@ -33,7 +68,7 @@ tetra_status check_desc(const tetra_desc* d) {
 
 tetra_status check_weights(int wtype, const float* w_scale) {
   if (wtype == TETRA_W_F32) return w_scale ? TETRA_ERR_ARG : TETRA_OK;
-  if (wtype == TETRA_W_F16) return w_scale ? TETRA_ERR_UNSUPPORTED : TETRA_ERR_ARG;
+  if (wtype == TETRA_W_F16) return w_scale ? TETRA_OK : TETRA_ERR_ARG;
   return TETRA_ERR_ARG;
 }
 
@@ -48,8 +83,13 @@ tetra_status tetra_dos_forward(const tetra_desc* d, const float* eps, const void
   if (!eps || !w || !dos) return TETRA_ERR_ARG;
   if ((st = check_weights(wtype, w_scale)) != TETRA_OK) return st;
   if (flags & ~(unsigned)TETRA_KAHAN) return TETRA_ERR_ARG;
-  if (flags & TETRA_KAHAN) return TETRA_ERR_UNSUPPORTED;
-  return hip_status(tetra::forward_f32(*d, eps, static_cast<const float*>(w), dos, (hipStream_t)stream));
+  void* scratch = nullptr;
+  if (flags & TETRA_KAHAN) {
+    const hipError_t e = exact_scratch(tetra::forward_exact_scratch_bytes(*d), &scratch);
+    if (e != hipSuccess) return hip_status(e);
+  }
+  return hip_status(
+      tetra::forward(*d, eps, w, wtype == TETRA_W_F16 ? w_scale : nullptr, dos, scratch, (hipStream_t)stream));
 }
 
 tetra_status tetra_dos_backward(const tetra_desc* d, const float* eps, const void* w, int wtype,
@@ -60,27 +100,32 @@ tetra_status tetra_dos_backward(const tetra_desc* d, const float* eps, const voi
   if (!eps || !w || !grad_dos || (!grad_eps && !grad_w)) return TETRA_ERR_ARG;
   if ((st = check_weights(wtype, w_scale)) != TETRA_OK) return st;
   if (flags & ~(unsigned)TETRA_KAHAN) return TETRA_ERR_ARG;
-  return hip_status(tetra::backward_f32(*d, eps, static_cast<const float*>(w), grad_dos, grad_eps, grad_w,
-                                        (hipStream_t)stream));
+  return hip_status(tetra::backward(*d, eps, w, wtype == TETRA_W_F16 ? w_scale : nullptr, grad_dos, grad_eps,
+                                    grad_w, (hipStream_t)stream));
 }
 
 size_t tetra_dos_batched_workspace(const tetra_item* items, int n, int wtype, unsigned flags) {
-  (void)items;
-  (void)n;
-  (void)wtype;
-  (void)flags;
-  return 0;
+  if (!items || n < 1 || (wtype != TETRA_W_F32 && wtype != TETRA_W_F16) || flags != 0) return 0;
+  for (int i = 0; i < n; ++i)
+    if (check_desc(&items[i].d) != TETRA_OK) return 0;
+  return 256 * tetra::batched_launches(items, n);
 }
 
 tetra_status tetra_dos_batched(const tetra_item* items, int n, int wtype, unsigned flags, void* workspace,
                                size_t ws_bytes, void* stream) {
   if (!items || n < 1) return TETRA_ERR_ARG;
-  (void)wtype;
-  (void)flags;
-  (void)workspace;
-  (void)ws_bytes;
-  (void)stream;
-  return TETRA_ERR_UNSUPPORTED;
+  if (wtype != TETRA_W_F32 && wtype != TETRA_W_F16) return TETRA_ERR_ARG;
+  if (flags & ~(unsigned)TETRA_KAHAN) return TETRA_ERR_ARG;
+  for (int i = 0; i < n; ++i) {
+    const tetra_item& it = items[i];
+    const tetra_status st = check_desc(&it.d);
+    if (st != TETRA_OK) return st;
+    if (!it.eps || !it.w || !it.dos) return TETRA_ERR_ARG;
+    if (check_weights(wtype, it.w_scale) != TETRA_OK) return TETRA_ERR_ARG;
+  }
+  if (flags & TETRA_KAHAN) return TETRA_ERR_UNSUPPORTED;
+  if (!workspace || ws_bytes < 256 * tetra::batched_launches(items, n)) return TETRA_ERR_WORKSPACE;
+  return hip_status(tetra::batched(items, n, wtype == TETRA_W_F16, workspace, (hipStream_t)stream));
 }
 
 const char* tetra_status_string(int status) {

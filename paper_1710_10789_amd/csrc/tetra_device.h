@@ -111,155 +111,175 @@ __host__ __device__ __forceinline__ float local_x(const TetSetup& c, int j, floa
   return __builtin_fmaf((float)j, de, c.d_hi) + c.d_lo;
 }
 
-// dw_l/dE at local energy x (0 < x < E41 assumed by the caller), sorted-corner order.
+// dw_l/dE at local energy x, sorted-corner order, one function per energy case:
+// A: 0 < x <= E21 (E1 < E <= E2), B: E21 < x <= E31 (E2 < E <= E3), C: E31 < x < E41 (E3 < E < E4).
+__host__ __device__ __forceinline__ void corner_dos_A(const TetSetup& c, float x, float g[4]) {
+  const float t = 4.0f * c.kA * x * x;
+  const float u = t * x;
+  g[0] = t * (3.0f - x * c.sA);
+  g[1] = u * c.r21;
+  g[2] = u * c.r31;
+  g[3] = u * c.r41;
+}
+
+__host__ __device__ __forceinline__ void corner_dos_B(const TetSetup& c, float x, float g[4]) {
+  const float z = x - c.e21, q = c.e31 - x, p = c.e41 - x;
+  const float C1 = c.k1 * x * x, dC1 = 2.0f * c.k1 * x;
+  const float C2 = c.k2 * x * z * q, dC2 = c.k2 * (x * q + z * q - x * z);
+  const float C3 = c.k3 * z * z * p, dC3 = c.k3 * z * (2.0f * p - z);
+  const float S12 = C1 + C2, D12 = dC1 + dC2, S23 = C2 + C3, D23 = dC2 + dC3;
+  const float S123 = S12 + C3, D123 = D12 + dC3;
+  g[0] = dC1 + (D12 * q - S12) * c.r31 + (D123 * p - S123) * c.r41;
+  g[1] = D123 + (D23 * q - S23) * c.r32 + (dC3 * p - C3) * c.r42;
+  g[2] = (D12 * x + S12) * c.r31 + (D23 * z + S23) * c.r32;
+  g[3] = (D123 * x + S123) * c.r41 + (dC3 * z + C3) * c.r42;
+}
+
+__host__ __device__ __forceinline__ void corner_dos_C(const TetSetup& c, float x, float g[4]) {
+  const float y = c.e41 - x;
+  const float t = 4.0f * c.kC * y * y;
+  const float u = t * y;
+  g[0] = u * c.r41;
+  g[1] = u * c.r42;
+  g[2] = u * c.r43;
+  g[3] = t * (3.0f - y * c.sC);
+}
+
+// dw_l/dE at local energy x (0 < x < E41 assumed by the caller).
 __host__ __device__ __forceinline__ void corner_dos(const TetSetup& c, float x, float g[4]) {
-  if (x <= c.e21) {  // E1 < E <= E2
-    const float t = 4.0f * c.kA * x * x;
-    const float u = t * x;
-    g[0] = t * (3.0f - x * c.sA);
-    g[1] = u * c.r21;
-    g[2] = u * c.r31;
-    g[3] = u * c.r41;
-  } else if (x <= c.e31) {  // E2 < E <= E3
-    const float z = x - c.e21, q = c.e31 - x, p = c.e41 - x;
-    const float C1 = c.k1 * x * x, dC1 = 2.0f * c.k1 * x;
-    const float C2 = c.k2 * x * z * q, dC2 = c.k2 * (x * q + z * q - x * z);
-    const float C3 = c.k3 * z * z * p, dC3 = c.k3 * z * (2.0f * p - z);
-    const float S12 = C1 + C2, D12 = dC1 + dC2, S23 = C2 + C3, D23 = dC2 + dC3;
-    const float S123 = S12 + C3, D123 = D12 + dC3;
-    g[0] = dC1 + (D12 * q - S12) * c.r31 + (D123 * p - S123) * c.r41;
-    g[1] = D123 + (D23 * q - S23) * c.r32 + (dC3 * p - C3) * c.r42;
-    g[2] = (D12 * x + S12) * c.r31 + (D23 * z + S23) * c.r32;
-    g[3] = (D123 * x + S123) * c.r41 + (dC3 * z + C3) * c.r42;
-  } else {  // E3 < E < E4
-    const float y = c.e41 - x;
-    const float t = 4.0f * c.kC * y * y;
-    const float u = t * y;
-    g[0] = u * c.r41;
-    g[1] = u * c.r42;
-    g[2] = u * c.r43;
-    g[3] = t * (3.0f - y * c.sC);
-  }
+  if (x <= c.e21) corner_dos_A(c, x, g);
+  else if (x <= c.e31) corner_dos_B(c, x, g);
+  else corner_dos_C(c, x, g);
 }
 
 // Corner weights g[4] (as corner_dos) and, for given multipliers s[4], the gradient
 // Eb[i] = d(sum_l s_l g_l)/dE_i with respect to the four sorted corner energies at fixed E, by reverse
 // accumulation through the same expressions as corner_dos.
-__host__ __device__ __forceinline__ void corner_dos_adjoint(const TetSetup& c, float V, float x, const float s[4], float g[4],
-                                                   float Eb[4]) {
-  if (x <= c.e21) {  // E1 < E <= E2
-    const float t = 4.0f * c.kA * x * x;
-    const float u = t * x;
-    g[0] = t * (3.0f - x * c.sA);
-    g[1] = u * c.r21;
-    g[2] = u * c.r31;
-    g[3] = u * c.r41;
-    float t_b = s[0] * (3.0f - x * c.sA);
-    float x_b = -s[0] * t * c.sA;
-    const float sA_b = -s[0] * t * x;
-    const float u_b = s[1] * c.r21 + s[2] * c.r31 + s[3] * c.r41;
-    float r21_b = s[1] * u, r31_b = s[2] * u, r41_b = s[3] * u;
-    t_b += u_b * x;
-    x_b += u_b * t;
-    const float kA_b = t_b * 4.0f * x * x;
-    x_b += t_b * 8.0f * c.kA * x;
-    r21_b += sA_b + kA_b * V * c.r31 * c.r41;
-    r31_b += sA_b + kA_b * V * c.r21 * c.r41;
-    r41_b += sA_b + kA_b * V * c.r21 * c.r31;
-    const float e21_b = -r21_b * c.r21 * c.r21, e31_b = -r31_b * c.r31 * c.r31, e41_b = -r41_b * c.r41 * c.r41;
-    Eb[0] = -(e21_b + e31_b + e41_b + x_b);
-    Eb[1] = e21_b;
-    Eb[2] = e31_b;
-    Eb[3] = e41_b;
-  } else if (x <= c.e31) {  // E2 < E <= E3
-    const float z = x - c.e21, q = c.e31 - x, p = c.e41 - x;
-    const float C1 = c.k1 * x * x, dC1 = 2.0f * c.k1 * x;
-    const float C2 = c.k2 * x * z * q, dC2 = c.k2 * (x * q + z * q - x * z);
-    const float C3 = c.k3 * z * z * p, dC3 = c.k3 * z * (2.0f * p - z);
-    const float S12 = C1 + C2, D12 = dC1 + dC2, S23 = C2 + C3, D23 = dC2 + dC3;
-    const float S123 = S12 + C3, D123 = D12 + dC3;
-    g[0] = dC1 + (D12 * q - S12) * c.r31 + (D123 * p - S123) * c.r41;
-    g[1] = D123 + (D23 * q - S23) * c.r32 + (dC3 * p - C3) * c.r42;
-    g[2] = (D12 * x + S12) * c.r31 + (D23 * z + S23) * c.r32;
-    g[3] = (D123 * x + S123) * c.r41 + (dC3 * z + C3) * c.r42;
-    // adjoints of the quantities the four outputs read
-    float dC1_b = s[0];
-    float D12_b = (s[0] * q + s[2] * x) * c.r31;
-    float S12_b = (s[2] - s[0]) * c.r31;
-    const float D123_b = s[0] * p * c.r41 + s[1] + s[3] * x * c.r41;
-    const float S123_b = (s[3] - s[0]) * c.r41;
-    const float D23_b = (s[1] * q + s[2] * z) * c.r32;
-    const float S23_b = (s[2] - s[1]) * c.r32;
-    float dC3_b = (s[1] * p + s[3] * z) * c.r42;
-    float C3_b = (s[3] - s[1]) * c.r42;
-    float q_b = s[0] * D12 * c.r31 + s[1] * D23 * c.r32;
-    float p_b = s[0] * D123 * c.r41 + s[1] * dC3 * c.r42;
-    float x_b = s[2] * D12 * c.r31 + s[3] * D123 * c.r41;
-    float z_b = s[2] * D23 * c.r32 + s[3] * dC3 * c.r42;
-    float r31_b = s[0] * (D12 * q - S12) + s[2] * (D12 * x + S12);
-    float r41_b = s[0] * (D123 * p - S123) + s[3] * (D123 * x + S123);
-    float r32_b = s[1] * (D23 * q - S23) + s[2] * (D23 * z + S23);
-    float r42_b = s[1] * (dC3 * p - C3) + s[3] * (dC3 * z + C3);
-    // partial sums
-    S12_b += S123_b;
-    C3_b += S123_b + S23_b;
-    D12_b += D123_b;
-    dC3_b += D123_b + D23_b;
-    const float C2_b = S23_b + S12_b;
-    const float dC2_b = D23_b + D12_b;
-    const float C1_b = S12_b;
-    dC1_b += D12_b;
-    // C3, dC3
-    const float k3_b = dC3_b * z * (2.0f * p - z) + C3_b * z * z * p;
-    z_b += dC3_b * c.k3 * (2.0f * p - 2.0f * z) + C3_b * 2.0f * c.k3 * z * p;
-    p_b += dC3_b * 2.0f * c.k3 * z + C3_b * c.k3 * z * z;
-    // C2, dC2
-    const float k2_b = dC2_b * (x * q + z * q - x * z) + C2_b * x * z * q;
-    x_b += dC2_b * c.k2 * (q - z) + C2_b * c.k2 * z * q;
-    q_b += dC2_b * c.k2 * (x + z) + C2_b * c.k2 * x * z;
-    z_b += dC2_b * c.k2 * (q - x) + C2_b * c.k2 * x * q;
-    // C1, dC1
-    float k1_b = dC1_b * 2.0f * x + C1_b * x * x;
-    x_b += dC1_b * 2.0f * c.k1 + C1_b * 2.0f * c.k1 * x;
-    // k1 = V r31 r41, k2 = k1 r32, k3 = V r32 r41 r42
-    k1_b += k2_b * c.r32;
-    r32_b += k2_b * c.k1 + k3_b * V * c.r41 * c.r42;
-    r41_b += k3_b * V * c.r32 * c.r42 + k1_b * V * c.r31;
-    const float r42_bb = r42_b + k3_b * V * c.r32 * c.r41;
-    r31_b += k1_b * V * c.r41;
-    const float e31_b = -r31_b * c.r31 * c.r31, e41_b = -r41_b * c.r41 * c.r41;
-    const float e32_b = -r32_b * c.r32 * c.r32, e42_b = -r42_bb * c.r42 * c.r42;
-    // x = E - E1, z = E - E2, q = E3 - E, p = E4 - E
-    Eb[0] = -x_b - e31_b - e41_b;
-    Eb[1] = -z_b - e32_b - e42_b;
-    Eb[2] = q_b + e31_b + e32_b;
-    Eb[3] = p_b + e41_b + e42_b;
-  } else {  // E3 < E < E4
-    const float y = c.e41 - x;
-    const float t = 4.0f * c.kC * y * y;
-    const float u = t * y;
-    g[0] = u * c.r41;
-    g[1] = u * c.r42;
-    g[2] = u * c.r43;
-    g[3] = t * (3.0f - y * c.sC);
-    float t_b = s[3] * (3.0f - y * c.sC);
-    float y_b = -s[3] * t * c.sC;
-    const float sC_b = -s[3] * t * y;
-    const float u_b = s[0] * c.r41 + s[1] * c.r42 + s[2] * c.r43;
-    float r41_b = s[0] * u, r42_b = s[1] * u, r43_b = s[2] * u;
-    t_b += u_b * y;
-    y_b += u_b * t;
-    const float kC_b = t_b * 4.0f * y * y;
-    y_b += t_b * 8.0f * c.kC * y;
-    r41_b += sC_b + kC_b * V * c.r42 * c.r43;
-    r42_b += sC_b + kC_b * V * c.r41 * c.r43;
-    r43_b += sC_b + kC_b * V * c.r41 * c.r42;
-    const float e41_b = -r41_b * c.r41 * c.r41, e42_b = -r42_b * c.r42 * c.r42, e43_b = -r43_b * c.r43 * c.r43;
-    Eb[0] = -e41_b;
-    Eb[1] = -e42_b;
-    Eb[2] = -e43_b;
-    Eb[3] = e41_b + e42_b + e43_b + y_b;
-  }
+// Corner weights g[4] (as corner_dos_*) and, for given multipliers s[4], the gradient
+// Eb[i] = d(sum_l s_l g_l)/dE_i with respect to the four sorted corner energies at fixed E, by reverse
+// accumulation through the same expressions; one function per energy case.
+__host__ __device__ __forceinline__ void corner_dos_adjoint_A(const TetSetup& c, float V, float x, const float s[4], float g[4], float Eb[4]) {
+  const float t = 4.0f * c.kA * x * x;
+  const float u = t * x;
+  g[0] = t * (3.0f - x * c.sA);
+  g[1] = u * c.r21;
+  g[2] = u * c.r31;
+  g[3] = u * c.r41;
+  float t_b = s[0] * (3.0f - x * c.sA);
+  float x_b = -s[0] * t * c.sA;
+  const float sA_b = -s[0] * t * x;
+  const float u_b = s[1] * c.r21 + s[2] * c.r31 + s[3] * c.r41;
+  float r21_b = s[1] * u, r31_b = s[2] * u, r41_b = s[3] * u;
+  t_b += u_b * x;
+  x_b += u_b * t;
+  const float kA_b = t_b * 4.0f * x * x;
+  x_b += t_b * 8.0f * c.kA * x;
+  r21_b += sA_b + kA_b * V * c.r31 * c.r41;
+  r31_b += sA_b + kA_b * V * c.r21 * c.r41;
+  r41_b += sA_b + kA_b * V * c.r21 * c.r31;
+  const float e21_b = -r21_b * c.r21 * c.r21, e31_b = -r31_b * c.r31 * c.r31, e41_b = -r41_b * c.r41 * c.r41;
+  Eb[0] = -(e21_b + e31_b + e41_b + x_b);
+  Eb[1] = e21_b;
+  Eb[2] = e31_b;
+  Eb[3] = e41_b;
+}
+
+__host__ __device__ __forceinline__ void corner_dos_adjoint_B(const TetSetup& c, float V, float x, const float s[4], float g[4], float Eb[4]) {
+  const float z = x - c.e21, q = c.e31 - x, p = c.e41 - x;
+  const float C1 = c.k1 * x * x, dC1 = 2.0f * c.k1 * x;
+  const float C2 = c.k2 * x * z * q, dC2 = c.k2 * (x * q + z * q - x * z);
+  const float C3 = c.k3 * z * z * p, dC3 = c.k3 * z * (2.0f * p - z);
+  const float S12 = C1 + C2, D12 = dC1 + dC2, S23 = C2 + C3, D23 = dC2 + dC3;
+  const float S123 = S12 + C3, D123 = D12 + dC3;
+  g[0] = dC1 + (D12 * q - S12) * c.r31 + (D123 * p - S123) * c.r41;
+  g[1] = D123 + (D23 * q - S23) * c.r32 + (dC3 * p - C3) * c.r42;
+  g[2] = (D12 * x + S12) * c.r31 + (D23 * z + S23) * c.r32;
+  g[3] = (D123 * x + S123) * c.r41 + (dC3 * z + C3) * c.r42;
+  // adjoints of the quantities the four outputs read
+  float dC1_b = s[0];
+  float D12_b = (s[0] * q + s[2] * x) * c.r31;
+  float S12_b = (s[2] - s[0]) * c.r31;
+  const float D123_b = s[0] * p * c.r41 + s[1] + s[3] * x * c.r41;
+  const float S123_b = (s[3] - s[0]) * c.r41;
+  const float D23_b = (s[1] * q + s[2] * z) * c.r32;
+  const float S23_b = (s[2] - s[1]) * c.r32;
+  float dC3_b = (s[1] * p + s[3] * z) * c.r42;
+  float C3_b = (s[3] - s[1]) * c.r42;
+  float q_b = s[0] * D12 * c.r31 + s[1] * D23 * c.r32;
+  float p_b = s[0] * D123 * c.r41 + s[1] * dC3 * c.r42;
+  float x_b = s[2] * D12 * c.r31 + s[3] * D123 * c.r41;
+  float z_b = s[2] * D23 * c.r32 + s[3] * dC3 * c.r42;
+  float r31_b = s[0] * (D12 * q - S12) + s[2] * (D12 * x + S12);
+  float r41_b = s[0] * (D123 * p - S123) + s[3] * (D123 * x + S123);
+  float r32_b = s[1] * (D23 * q - S23) + s[2] * (D23 * z + S23);
+  float r42_b = s[1] * (dC3 * p - C3) + s[3] * (dC3 * z + C3);
+  // partial sums
+  S12_b += S123_b;
+  C3_b += S123_b + S23_b;
+  D12_b += D123_b;
+  dC3_b += D123_b + D23_b;
+  const float C2_b = S23_b + S12_b;
+  const float dC2_b = D23_b + D12_b;
+  const float C1_b = S12_b;
+  dC1_b += D12_b;
+  // C3, dC3
+  const float k3_b = dC3_b * z * (2.0f * p - z) + C3_b * z * z * p;
+  z_b += dC3_b * c.k3 * (2.0f * p - 2.0f * z) + C3_b * 2.0f * c.k3 * z * p;
+  p_b += dC3_b * 2.0f * c.k3 * z + C3_b * c.k3 * z * z;
+  // C2, dC2
+  const float k2_b = dC2_b * (x * q + z * q - x * z) + C2_b * x * z * q;
+  x_b += dC2_b * c.k2 * (q - z) + C2_b * c.k2 * z * q;
+  q_b += dC2_b * c.k2 * (x + z) + C2_b * c.k2 * x * z;
+  z_b += dC2_b * c.k2 * (q - x) + C2_b * c.k2 * x * q;
+  // C1, dC1
+  float k1_b = dC1_b * 2.0f * x + C1_b * x * x;
+  x_b += dC1_b * 2.0f * c.k1 + C1_b * 2.0f * c.k1 * x;
+  // k1 = V r31 r41, k2 = k1 r32, k3 = V r32 r41 r42
+  k1_b += k2_b * c.r32;
+  r32_b += k2_b * c.k1 + k3_b * V * c.r41 * c.r42;
+  r41_b += k3_b * V * c.r32 * c.r42 + k1_b * V * c.r31;
+  const float r42_bb = r42_b + k3_b * V * c.r32 * c.r41;
+  r31_b += k1_b * V * c.r41;
+  const float e31_b = -r31_b * c.r31 * c.r31, e41_b = -r41_b * c.r41 * c.r41;
+  const float e32_b = -r32_b * c.r32 * c.r32, e42_b = -r42_bb * c.r42 * c.r42;
+  // x = E - E1, z = E - E2, q = E3 - E, p = E4 - E
+  Eb[0] = -x_b - e31_b - e41_b;
+  Eb[1] = -z_b - e32_b - e42_b;
+  Eb[2] = q_b + e31_b + e32_b;
+  Eb[3] = p_b + e41_b + e42_b;
+}
+
+__host__ __device__ __forceinline__ void corner_dos_adjoint_C(const TetSetup& c, float V, float x, const float s[4], float g[4], float Eb[4]) {
+  const float y = c.e41 - x;
+  const float t = 4.0f * c.kC * y * y;
+  const float u = t * y;
+  g[0] = u * c.r41;
+  g[1] = u * c.r42;
+  g[2] = u * c.r43;
+  g[3] = t * (3.0f - y * c.sC);
+  float t_b = s[3] * (3.0f - y * c.sC);
+  float y_b = -s[3] * t * c.sC;
+  const float sC_b = -s[3] * t * y;
+  const float u_b = s[0] * c.r41 + s[1] * c.r42 + s[2] * c.r43;
+  float r41_b = s[0] * u, r42_b = s[1] * u, r43_b = s[2] * u;
+  t_b += u_b * y;
+  y_b += u_b * t;
+  const float kC_b = t_b * 4.0f * y * y;
+  y_b += t_b * 8.0f * c.kC * y;
+  r41_b += sC_b + kC_b * V * c.r42 * c.r43;
+  r42_b += sC_b + kC_b * V * c.r41 * c.r43;
+  r43_b += sC_b + kC_b * V * c.r41 * c.r42;
+  const float e41_b = -r41_b * c.r41 * c.r41, e42_b = -r42_b * c.r42 * c.r42, e43_b = -r43_b * c.r43 * c.r43;
+  Eb[0] = -e41_b;
+  Eb[1] = -e42_b;
+  Eb[2] = -e43_b;
+  Eb[3] = e41_b + e42_b + e43_b + y_b;
+}
+
+__host__ __device__ __forceinline__ void corner_dos_adjoint(const TetSetup& c, float V, float x, const float s[4], float g[4], float Eb[4]) {
+  if (x <= c.e21) corner_dos_adjoint_A(c, V, x, s, g, Eb);
+  else if (x <= c.e31) corner_dos_adjoint_B(c, V, x, s, g, Eb);
+  else corner_dos_adjoint_C(c, V, x, s, g, Eb);
 }
 
 // Estimate of the window of grid indices j with E1 < E_j < E4, clipped to [lo, hi] (empty when
@@ -267,7 +287,7 @@ __host__ __device__ __forceinline__ void corner_dos_adjoint(const TetSetup& c, f
 // tet_window to make it exact for one tetrahedron-band.
 __host__ __device__ __forceinline__ void energy_window(float e1, float e4, float e0, float inv_de, int lo, int hi,
                                                        int& jlo, int& jhi) {
-  const float big = 3.0e7f;  // beyond any supported grid length (ne < 2^24)
+  const float big = 3.0e7f;  // beyond any supported grid length
   float t1 = (e1 - e0) * inv_de;
   float t4 = (e4 - e0) * inv_de;
   t1 = fminf(fmaxf(t1, -2.0f), big);
@@ -277,13 +297,36 @@ __host__ __device__ __forceinline__ void energy_window(float e1, float e4, float
   jhi = b < hi ? b : hi;
 }
 
-// Exact window {j in [lo, hi] : 0 < x_j < E41} of one tetrahedron-band, from the estimate and the
-// accurate local-frame x. A boundary index matters for the gradient: the derivative of the corner
+// Exact window {j in [lo, hi] : 0 < x_j < E41} of one tetrahedron-band, from the estimate (off by at
+// most one index at either end for ne <= 2^22) and the accurate local-frame x, which is
+// non-decreasing in j. A boundary index matters for the gradient: the derivative of the corner
 // weights with respect to E1 (or E4) vanishes only linearly in x (or E4 - E_j), with a prefactor
 // 1/(E21 E31 E41) that is large for narrow tetrahedra.
 __host__ __device__ __forceinline__ void tet_window(const TetSetup& c, float de, int lo, int hi, int& jlo, int& jhi) {
-  if (jlo > lo && local_x(c, jlo - 1, de) > 0.0f) --jlo;
-  if (jhi < hi && local_x(c, jhi + 1, de) < c.e41) ++jhi;
+  if (jlo <= hi && !(local_x(c, jlo, de) > 0.0f)) ++jlo;
+  else if (jlo > lo && local_x(c, jlo - 1, de) > 0.0f) --jlo;
+  if (jhi >= lo && !(local_x(c, jhi, de) < c.e41)) --jhi;
+  else if (jhi < hi && local_x(c, jhi + 1, de) < c.e41) ++jhi;
+}
+
+// Last j in [jlo, jhi] with x_j <= thr (jlo - 1 if none), for x_j non-decreasing in j.
+__host__ __device__ __forceinline__ int last_at_or_below(const TetSetup& c, float de, float inv_de, int jlo, int jhi,
+                                                         float thr) {
+  const float x0 = local_x(c, jlo, de);
+  float t = (thr - x0) * inv_de;
+  t = fminf(fmaxf(t, -1.0f), (float)(jhi - jlo));
+  int j = jlo + (int)floorf(t);
+  if (j >= jlo && local_x(c, j, de) > thr) --j;
+  else if (j < jhi && local_x(c, j + 1, de) <= thr) ++j;
+  return j;
+}
+
+// Case boundaries inside the window: [jlo, jA] first case, (jA, jB] middle case, (jB, jhi] third case.
+__host__ __device__ __forceinline__ void case_split(const TetSetup& c, float de, float inv_de, int jlo, int jhi,
+                                                    int& jA, int& jB) {
+  jA = last_at_or_below(c, de, inv_de, jlo, jhi, c.e21);
+  jB = last_at_or_below(c, de, inv_de, jlo, jhi, c.e31);
+  if (jB < jA) jB = jA;
 }
 
 // Estimate of the energy range of a set of grid points, one index wider on each side than

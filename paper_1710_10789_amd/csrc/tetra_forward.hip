@@ -21,7 +21,10 @@
 //    B = sum 12 V bmax / E41 over the tetrahedra with a non-empty window bounds every bin's |sum| and
 //    fixes a power-of-two scale S with B*S <= 2^62 (two's complement, so signed weights work too).
 //    The in-LDS sum is then exact and independent of the order of the atomics; the only rounding
-//    left is that of each FP32 contribution;
+//    left is that of each FP32 contribution. When the tile's weights are non-negative and its bound
+//    is not dominated by narrow tetrahedra (E41 < 2 de, whose spikes would make B loose), two orbitals
+//    share one 64-bit atomic as two 32-bit fields with B*S <= 2^30 (no carry between fields), which
+//    halves the LDS atomic traffic;
 //  * one global float atomic per touched (energy, orbital) bin when the workgroup finishes.
 // Workgroups are assigned so that each XCD (eight per MI355X, each with its own L2) works through a
 // contiguous range of tiles of the same band, keeping shared halo points in one L2.
@@ -38,12 +41,16 @@ constexpr int NT = TX * TY * TZ;        // one lane per cube
 constexpr int PX = TX + 1, PY = TY + 1, PZ = TZ + 1;
 constexpr int NP = PX * PY * PZ;  // staged grid points (cube corners of the tile)
 constexpr int HCAP = 2048;        // LDS histogram capacity in 64-bit words
+constexpr int CP = 1;             // histogram copies (lane % CP picks one) to spread same-bin atomics
 constexpr int NXCD = 8;
 
 struct FwdArgs {
   const float* eps;
-  const float* w;
+  const void* w;        // float or _Float16 [nb][norb][nk]
+  const float* w_scale;  // per-band scale of _Float16 weights
   float* dos;
+  float* gbound;                // exact mode: sum of the per-workgroup bounds (accumulated in mode 1)
+  unsigned long long* gacc;     // exact mode: [ne][norb] 64-bit fixed-point sums (mode 2)
   int n1, n2, n3, ne;
   float e0, de, inv_de, V;
   int t1, t2, t3;  // tiles along each axis
@@ -72,18 +79,17 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-template <int NORB>
-__global__ __launch_bounds__(NT) void dos_forward_kernel(FwdArgs a) {
-  constexpr int LC = ((HCAP / NORB) - 1) & ~1;  // energies per histogram pass (even)
+// One work unit (tile, band) of the forward pass; every lane of the workgroup calls it.
+// MODE 0: DOS with per-workgroup scales; 1: only add this workgroup's bound to *gbound;
+// 2: DOS in the common scale fixed by *gbound, summed exactly into gacc with 64-bit global atomics.
+template <int NORB, typename WT, int MODE>
+__device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
+  constexpr int LC = ((HCAP / (NORB * CP)) - 1) & ~1;  // energies per histogram pass (even)
   __shared__ float s_eps[NP];
   __shared__ float s_w[NP * NORB];
   __shared__ unsigned long long s_hist[HCAP];
-  __shared__ float s_red[3 * (NT / 64)];
+  __shared__ float s_red[4 * (NT / 64)];
 
-  // XCD-aware mapping: hardware dispatches block b to XCD b % 8; give each XCD a contiguous range.
-  const int b = blockIdx.x;
-  const int unit = (b % NXCD) * a.per_xcd + b / NXCD;
-  if (unit >= a.nunits) return;
   const int band = unit / a.ntiles;
   const int tile = unit - band * a.ntiles;
   const int tz = tile % a.t3;
@@ -93,10 +99,11 @@ __global__ __launch_bounds__(NT) void dos_forward_kernel(FwdArgs a) {
   const int tid = threadIdx.x;
   const int64_t nk = (int64_t)a.n1 * a.n2 * a.n3;
   const float* eps_n = a.eps + (int64_t)band * nk;
-  const float* w_n = a.w + (int64_t)band * NORB * nk;
+  const WT* w_n = static_cast<const WT*>(a.w) + (int64_t)band * NORB * nk;
+  const float wscale = a.w_scale ? a.w_scale[band] : 1.0f;
 
   // Stage the tile's grid points (periodic wrap) and find their energy range.
-  float lmin = __builtin_huge_valf(), lmax = -__builtin_huge_valf(), lbmax = 0.0f;
+  float lmin = __builtin_huge_valf(), lmax = -__builtin_huge_valf(), lbmax = 0.0f, lbmin = 0.0f;
   for (int p = tid; p < NP; p += NT) {
     const int pz = p % PZ, py = (p / PZ) % PY, px = p / (PZ * PY);
     const int64_t k = ((int64_t)wrap(x0 + px, a.n1) * a.n2 + wrap(y0 + py, a.n2)) * a.n3 + wrap(z0 + pz, a.n3);
@@ -108,26 +115,30 @@ __global__ __launch_bounds__(NT) void dos_forward_kernel(FwdArgs a) {
     }
 #pragma unroll
     for (int m = 0; m < NORB; ++m) {
-      const float b = w_n[(int64_t)m * nk + k];
+      const float b = (float)w_n[(int64_t)m * nk + k] * wscale;
       s_w[p * NORB + m] = b;
       lbmax = fmaxf(lbmax, fabsf(b));
+      lbmin = fminf(lbmin, b);
     }
   }
   lmin = wave_min(lmin);
   lmax = wave_max(lmax);
   lbmax = wave_max(lbmax);
+  lbmin = wave_min(lbmin);
   if ((tid & 63) == 0) {
     s_red[tid >> 6] = lmin;
     s_red[(NT / 64) + (tid >> 6)] = lmax;
     s_red[2 * (NT / 64) + (tid >> 6)] = lbmax;
+    s_red[3 * (NT / 64) + (tid >> 6)] = lbmin;
   }
   __syncthreads();
-  float emin = s_red[0], emax = s_red[NT / 64], bmax = s_red[2 * (NT / 64)];
+  float emin = s_red[0], emax = s_red[NT / 64], bmax = s_red[2 * (NT / 64)], bmin = s_red[3 * (NT / 64)];
 #pragma unroll
   for (int i = 1; i < NT / 64; ++i) {
     emin = fminf(emin, s_red[i]);
     emax = fmaxf(emax, s_red[NT / 64 + i]);
     bmax = fmaxf(bmax, s_red[2 * (NT / 64) + i]);
+    bmin = fminf(bmin, s_red[3 * (NT / 64) + i]);
   }
   if (!(emin <= emax)) return;  // no finite energy in this tile-band (uniform across the block)
   int J0, J1;
@@ -140,8 +151,8 @@ __global__ __launch_bounds__(NT) void dos_forward_kernel(FwdArgs a) {
   auto point_offset = [](int s) { return (s & 1) * (PY * PZ) + ((s >> 1) & 1) * PZ + (s >> 2); };
 
   // Bound on any bin's sum: sum over tetrahedra with a possibly non-empty window of 12 V bmax / E41.
-  float bound = 0.0f;
-  if (valid) {
+  float bound = 0.0f, narrow = 0.0f;
+  if (MODE != 2 && valid) {
 #pragma unroll 1
     for (int t = 0; t < 6; ++t) {
       const uint32_t slots = tet_slots(t);
@@ -158,28 +169,46 @@ __global__ __launch_bounds__(NT) void dos_forward_kernel(FwdArgs a) {
       int jlo, jhi;
       energy_window(lo, hi, a.e0, a.inv_de, J0, J1, jlo, jhi);
       if (jlo > jhi + 2) continue;
-      bound += 12.0f * a.V * bmax / (hi - lo);
+      const float term = 12.0f * a.V * bmax / (hi - lo);
+      bound += term;
+      if (hi - lo < 2.0f * a.de) narrow += term;
     }
   }
   bound = wave_sum(fminf(bound, 1.0e37f));
+  narrow = wave_sum(fminf(narrow, 1.0e37f));
   __syncthreads();  // every lane has read s_red
-  if ((tid & 63) == 0) s_red[tid >> 6] = bound;
+  if ((tid & 63) == 0) {
+    s_red[tid >> 6] = bound;
+    s_red[(NT / 64) + (tid >> 6)] = narrow;
+  }
   __syncthreads();
-  float B = 0.0f;
+  float B = 0.0f, Bn = 0.0f;
 #pragma unroll
-  for (int i = 0; i < NT / 64; ++i) B += s_red[i];
+  for (int i = 0; i < NT / 64; ++i) {
+    B += s_red[i];
+    Bn += s_red[NT / 64 + i];
+  }
+  if (MODE == 1) {
+    if (tid == 0 && B > 0.0f) atomic_add_global(a.gbound, B);
+    return;
+  }
+  if (MODE == 2) B = 1.0001f * *a.gbound;  // margin for the rounding of the float sum
   if (!(B > 0.0f)) return;  // nothing to add (uniform across the block)
+  const bool packed = MODE == 0 && bmin >= 0.0f && Bn <= 0.5f * B;  // uniform across the block
+  constexpr int NPAIR = (NORB + 1) / 2;
+  const int rows = packed ? NPAIR : NORB;  // histogram rows of 64-bit words
   int bexp;
   frexpf(fminf(B, 3.0e38f), &bexp);  // B <= 2^bexp
-  const int sexp = min(62 - bexp, 126);
-  const float S = ldexpf(1.0f, sexp);        // B * S <= 2^62
+  const int sexp = min((packed ? 30 : 62) - bexp, 126);
+  const float S = ldexpf(1.0f, sexp);  // B * S <= 2^30 (packed) or 2^62
   const double inv_S = ldexp(1.0, -sexp);
+  const int cp = tid % CP;
 
   for (int c0 = J0; c0 <= J1; c0 += LC) {
     const int c1 = min(c0 + LC - 1, J1);
     const int L = c1 - c0 + 1;
     const int LP = L | 1;  // odd row pitch: the flush reads across orbitals without bank conflicts
-    for (int q = tid; q < NORB * LP; q += NT) s_hist[q] = 0ull;
+    for (int q = tid; q < rows * LP * CP; q += NT) s_hist[q] = 0ull;
     __syncthreads();
     if (valid) {
 #pragma unroll 1
@@ -207,38 +236,220 @@ __global__ __launch_bounds__(NT) void dos_forward_kernel(FwdArgs a) {
 #pragma unroll
           for (int m = 0; m < NORB; ++m) bb[l][m] = s_w[p * NORB + m];
         }
-        for (int j = jlo; j <= jhi; ++j) {
-          const float x = local_x(cs, j, a.de);
-          if (!(x > 0.0f && x < cs.e41)) continue;
-          float g[4];
-          corner_dos(cs, x, g);
-          unsigned long long* h = &s_hist[j - c0];
+        // The window splits into the three energy cases; each sub-loop runs one case only, so lanes of
+        // a wavefront do not execute the other cases' code.
+        int jA, jB;
+        case_split(cs, a.de, a.inv_de, jlo, jhi, jA, jB);
+        auto deposit = [&](int j, const float g[4]) {
+          unsigned long long* h = &s_hist[(j - c0) * CP + cp];
+          if (packed) {
 #pragma unroll
-          for (int m = 0; m < NORB; ++m) {
-            const float v = g[0] * bb[0][m] + g[1] * bb[1][m] + g[2] * bb[2][m] + g[3] * bb[3][m];
-            atomicAdd(&h[m * LP], (unsigned long long)__float2ll_rn(v * S));
+            for (int pr = 0; pr < NPAIR; ++pr) {
+              const int m0 = 2 * pr, m1 = 2 * pr + 1;
+              const float v0 = g[0] * bb[0][m0] + g[1] * bb[1][m0] + g[2] * bb[2][m0] + g[3] * bb[3][m0];
+              unsigned long long word = (unsigned long long)__float2uint_rn(v0 * S);
+              if (m1 < NORB) {
+                const float v1 = g[0] * bb[0][m1] + g[1] * bb[1][m1] + g[2] * bb[2][m1] + g[3] * bb[3][m1];
+                word |= (unsigned long long)__float2uint_rn(v1 * S) << 32;
+              }
+              atomicAdd(&h[pr * LP * CP], word);
+            }
+          } else {
+#pragma unroll
+            for (int m = 0; m < NORB; ++m) {
+              const float v = g[0] * bb[0][m] + g[1] * bb[1][m] + g[2] * bb[2][m] + g[3] * bb[3][m];
+              atomicAdd(&h[m * LP * CP], (unsigned long long)__float2ll_rn(v * S));
+            }
           }
+        };
+        for (int j = jlo; j <= jA; ++j) {
+          float g[4];
+          corner_dos_A(cs, local_x(cs, j, a.de), g);
+          deposit(j, g);
+        }
+        for (int j = jA + 1; j <= jB; ++j) {
+          float g[4];
+          corner_dos_B(cs, local_x(cs, j, a.de), g);
+          deposit(j, g);
+        }
+        for (int j = jB + 1; j <= jhi; ++j) {
+          float g[4];
+          corner_dos_C(cs, local_x(cs, j, a.de), g);
+          deposit(j, g);
         }
       }
     }
     __syncthreads();
     for (int q = tid; q < L * NORB; q += NT) {
       const int r = q / NORB, m = q - r * NORB;
-      const unsigned long long qv = s_hist[m * LP + r];
-      if (qv != 0ull) atomic_add_global(&a.dos[(int64_t)(c0 + r) * NORB + m], (float)((double)(long long)qv * inv_S));
+      const int row = packed ? (m >> 1) : m;
+      double sum = 0.0;
+#pragma unroll
+      for (int c = 0; c < CP; ++c) {
+        const unsigned long long w = s_hist[(row * LP + r) * CP + c];
+        if (packed) sum += (double)(unsigned)((m & 1) ? (w >> 32) : (w & 0xffffffffull));
+        else sum += (double)(long long)w;
+      }
+      if (MODE == 2) {
+        const unsigned long long w = s_hist[(row * LP + r) * CP];
+        unsigned long long tot = w;
+#pragma unroll
+        for (int c = 1; c < CP; ++c) tot += s_hist[(row * LP + r) * CP + c];
+        if (tot != 0ull) atomicAdd(&a.gacc[(int64_t)(c0 + r) * NORB + m], tot);
+      } else if (sum != 0.0) {
+        atomic_add_global(&a.dos[(int64_t)(c0 + r) * NORB + m], (float)(sum * inv_S));
+      }
     }
     __syncthreads();
   }
 }
+
+template <int NORB, typename WT, int MODE>
+__global__ __launch_bounds__(NT) void dos_forward_kernel(FwdArgs a) {
+  // XCD-aware mapping: hardware dispatches block b to XCD b % 8; give each XCD a contiguous range.
+  const int b = blockIdx.x;
+  const int unit = (b % NXCD) * a.per_xcd + b / NXCD;
+  if (unit < a.nunits) forward_unit<NORB, WT, MODE>(a, unit);
+}
+
 
 __global__ void fill_zero_kernel(float* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0.0f;
 }
 
+// ---------------------------------------------------------------------------------------------
+// Batched forward: one persistent launch over the flattened (item, band, tile) work queue of up to
+// kMaxBatch problems with the same orbital count. Workgroups pull units from an atomic counter in the
+// caller's workspace, so problems of very different sizes balance across the chip.
+
+struct BatchItem {
+  const float* eps;
+  const void* w;
+  const float* w_scale;
+  float* dos;
+  int n1, n2, n3, ne;
+  float e0, de;
+  int t1, t2, t3, ntiles;
+  int unit_begin;  // first global unit of this item (items in order, units band-major)
+};
+
+struct BatchArgs {
+  int n, total;
+  unsigned* counter;
+  BatchItem it[kMaxBatch];
+};
+
+template <int NORB, typename WT>
+__global__ __launch_bounds__(NT) void dos_batched_kernel(BatchArgs b) {
+  __shared__ int s_unit;
+  for (;;) {
+    __syncthreads();  // the previous unit's LDS reads are done
+    if (threadIdx.x == 0) s_unit = (int)atomicAdd(b.counter, 1u);
+    __syncthreads();
+    const int u = s_unit;
+    if (u >= b.total) return;  // every lane read the same u: the whole workgroup leaves
+    int i = 0;
+    while (i + 1 < b.n && b.it[i + 1].unit_begin <= u) ++i;
+    const BatchItem& it = b.it[i];
+    FwdArgs a;
+    a.eps = it.eps;
+    a.w = it.w;
+    a.w_scale = it.w_scale;
+    a.dos = it.dos;
+    a.gbound = nullptr;
+    a.gacc = nullptr;
+    a.n1 = it.n1;
+    a.n2 = it.n2;
+    a.n3 = it.n3;
+    a.ne = it.ne;
+    a.e0 = it.e0;
+    a.de = it.de;
+    a.inv_de = 1.0f / it.de;
+    a.V = (float)(1.0 / (24.0 * (double)it.n1 * it.n2 * it.n3));
+    a.t1 = it.t1;
+    a.t2 = it.t2;
+    a.t3 = it.t3;
+    a.ntiles = it.ntiles;
+    a.nunits = 0;
+    a.per_xcd = 0;
+    forward_unit<NORB, WT, 0>(a, u - it.unit_begin);
+  }
+}
+
+// Zero every item's DOS (blockIdx.y = item) and the work counter.
+__global__ void batched_zero_kernel(BatchArgs b, int norb) {
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *b.counter = 0u;
+  const BatchItem& it = b.it[blockIdx.y];
+  const int64_t n = (int64_t)it.ne * norb;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    it.dos[i] = 0.0f;
+}
+
+template <int NORB>
+hipError_t launch_batched(const BatchArgs& b, bool half, hipStream_t s) {
+  hipLaunchKernelGGL(batched_zero_kernel, dim3(64, b.n), dim3(256), 0, s, b, NORB);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  static int per_cu[2] = {0, 0};
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+  }
+  int& occ = per_cu[half ? 1 : 0];
+  if (!occ) {
+    e = half ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, dos_batched_kernel<NORB, _Float16>, NT, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, dos_batched_kernel<NORB, float>, NT, 0);
+    if (e != hipSuccess) return e;
+    if (occ < 1) occ = 1;
+  }
+  const int grid = std::min(b.total, occ * cus);
+  if (half)
+    hipLaunchKernelGGL((dos_batched_kernel<NORB, _Float16>), dim3(grid), dim3(NT), 0, s, b);
+  else
+    hipLaunchKernelGGL((dos_batched_kernel<NORB, float>), dim3(grid), dim3(NT), 0, s, b);
+  return hipGetLastError();
+}
+
+template <int NORB, int MODE>
+hipError_t launch_fwd_mode(const FwdArgs& a, int grid, hipStream_t s) {
+  if (a.w_scale)
+    hipLaunchKernelGGL((dos_forward_kernel<NORB, _Float16, MODE>), dim3(grid), dim3(NT), 0, s, a);
+  else
+    hipLaunchKernelGGL((dos_forward_kernel<NORB, float, MODE>), dim3(grid), dim3(NT), 0, s, a);
+  return hipGetLastError();
+}
+
+__global__ void fill_zero_u64_kernel(unsigned long long* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+
+// dos = gacc / S with S the common scale of mode 2.
+__global__ void fixed_to_float_kernel(const unsigned long long* acc, const float* gbound, float* dos, int64_t n) {
+  const float B = 1.0001f * *gbound;
+  double inv_S = 0.0;
+  if (B > 0.0f) {
+    int bexp;
+    frexpf(fminf(B, 3.0e38f), &bexp);
+    inv_S = ldexp(1.0, -min(62 - bexp, 126));
+  }
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dos[i] = (float)((double)(long long)acc[i] * inv_S);
+}
+
 template <int NORB>
 hipError_t launch_fwd(const FwdArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(dos_forward_kernel<NORB>, dim3(grid), dim3(NT), 0, s, a);
+  if (!a.gacc) return launch_fwd_mode<NORB, 0>(a, grid, s);
+  hipError_t e = launch_fwd_mode<NORB, 1>(a, grid, s);
+  if (e != hipSuccess) return e;
+  e = launch_fwd_mode<NORB, 2>(a, grid, s);
+  if (e != hipSuccess) return e;
+  const int64_t n = (int64_t)a.ne * NORB;
+  hipLaunchKernelGGL(fixed_to_float_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, s,
+                     a.gacc, a.gbound, a.dos, n);
   return hipGetLastError();
 }
 
@@ -251,10 +462,15 @@ hipError_t fill_zero(float* p, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t forward_f32(const tetra_desc& d, const float* eps, const float* w, float* dos, hipStream_t s) {
+hipError_t forward(const tetra_desc& d, const float* eps, const void* w, const float* w_scale, float* dos,
+                   void* exact_scratch, hipStream_t s) {
   FwdArgs a;
+  // exact_scratch (exact mode): 256 bytes holding the bound, then ne*norb 64-bit sums
+  a.gbound = exact_scratch ? static_cast<float*>(exact_scratch) : nullptr;
+  a.gacc = exact_scratch ? reinterpret_cast<unsigned long long*>(static_cast<char*>(exact_scratch) + 256) : nullptr;
   a.eps = eps;
   a.w = w;
+  a.w_scale = w_scale;
   a.dos = dos;
   a.n1 = d.n1;
   a.n2 = d.n2;
@@ -271,7 +487,17 @@ hipError_t forward_f32(const tetra_desc& d, const float* eps, const float* w, fl
   a.nunits = a.ntiles * d.nb;
   a.per_xcd = (a.nunits + NXCD - 1) / NXCD;
   const int grid = a.per_xcd * NXCD;
-  hipError_t e = fill_zero(dos, (int64_t)d.ne * d.norb, s);
+  hipError_t e = hipSuccess;
+  if (exact_scratch) {
+    e = fill_zero(a.gbound, 1, s);
+    if (e != hipSuccess) return e;
+    const int64_t n = (int64_t)d.ne * d.norb;
+    hipLaunchKernelGGL(fill_zero_u64_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, s,
+                       a.gacc, n);
+    e = hipGetLastError();
+  } else {
+    e = fill_zero(dos, (int64_t)d.ne * d.norb, s);
+  }
   if (e != hipSuccess) return e;
   switch (d.norb) {
 #define TETRA_CASE(N) \
@@ -284,6 +510,69 @@ hipError_t forward_f32(const tetra_desc& d, const float* eps, const float* w, fl
     default:
       return hipErrorInvalidValue;
   }
+}
+
+size_t batched_launches(const tetra_item* items, int n) {
+  size_t launches = 0;
+  for (int norb = 1; norb <= 16; ++norb) {
+    int cnt = 0;
+    for (int i = 0; i < n; ++i) cnt += items[i].d.norb == norb;
+    launches += (cnt + kMaxBatch - 1) / kMaxBatch;
+  }
+  return launches;
+}
+
+hipError_t batched(const tetra_item* items, int n, bool half, void* workspace, hipStream_t s) {
+  unsigned* counters = static_cast<unsigned*>(workspace);
+  int launch = 0;
+  for (int norb = 1; norb <= 16; ++norb) {
+    BatchArgs b;
+    b.n = 0;
+    b.total = 0;
+    for (int i = 0; i <= n; ++i) {
+      const bool flush = (i == n && b.n > 0) || b.n == kMaxBatch;
+      if (flush) {
+        b.counter = counters + 64 * launch++;  // one 256-byte line per launch
+        hipError_t e = hipSuccess;
+        switch (norb) {
+#define TETRA_CASE(N) \
+  case N:             \
+    e = launch_batched<N>(b, half, s); \
+    break;
+          TETRA_CASE(1) TETRA_CASE(2) TETRA_CASE(3) TETRA_CASE(4) TETRA_CASE(5) TETRA_CASE(6) TETRA_CASE(7)
+          TETRA_CASE(8) TETRA_CASE(9) TETRA_CASE(10) TETRA_CASE(11) TETRA_CASE(12) TETRA_CASE(13)
+          TETRA_CASE(14) TETRA_CASE(15) TETRA_CASE(16)
+#undef TETRA_CASE
+          default:
+            e = hipErrorInvalidValue;
+        }
+        if (e != hipSuccess) return e;
+        b.n = 0;
+        b.total = 0;
+      }
+      if (i == n) break;
+      const tetra_desc& d = items[i].d;
+      if (d.norb != norb) continue;
+      BatchItem& it = b.it[b.n++];
+      it.eps = items[i].eps;
+      it.w = items[i].w;
+      it.w_scale = half ? items[i].w_scale : nullptr;
+      it.dos = items[i].dos;
+      it.n1 = d.n1;
+      it.n2 = d.n2;
+      it.n3 = d.n3;
+      it.ne = d.ne;
+      it.e0 = d.e0;
+      it.de = d.de;
+      it.t1 = (d.n1 + TX - 1) / TX;
+      it.t2 = (d.n2 + TY - 1) / TY;
+      it.t3 = (d.n3 + TZ - 1) / TZ;
+      it.ntiles = it.t1 * it.t2 * it.t3;
+      it.unit_begin = b.total;
+      b.total += it.ntiles * d.nb;
+    }
+  }
+  return hipSuccess;
 }
 
 }  // namespace tetra

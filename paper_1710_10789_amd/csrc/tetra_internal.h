@@ -8,9 +8,19 @@
 
 namespace tetra {
 
+constexpr int kMaxBatch = 32;  // problems per persistent batched launch
+
 hipError_t fill_zero(float* p, int64_t n, hipStream_t s);
-hipError_t forward_f32(const tetra_desc& d, const float* eps, const float* w, float* dos, hipStream_t s);
-hipError_t backward_f32(const tetra_desc& d, const float* eps, const float* w, const float* G, float* grad_eps,
-                        float* grad_w, hipStream_t s);
+// w is float, or _Float16 when w_scale (per-band scale) is non-null. exact_scratch (or null) is device
+// memory of forward_exact_scratch_bytes(d) for the exact cross-workgroup accumulation.
+hipError_t forward(const tetra_desc& d, const float* eps, const void* w, const float* w_scale, float* dos,
+                   void* exact_scratch, hipStream_t s);
+// Batched forward: items grouped by orbital count, up to kMaxBatch per persistent launch. The
+// workspace holds one 256-byte work counter per launch.
+size_t batched_launches(const tetra_item* items, int n);
+hipError_t batched(const tetra_item* items, int n, bool half, void* workspace, hipStream_t s);
+inline size_t forward_exact_scratch_bytes(const tetra_desc& d) { return 256 + 8 * (size_t)d.ne * d.norb; }
+hipError_t backward(const tetra_desc& d, const float* eps, const void* w, const float* w_scale, const float* G,
+                    float* grad_eps, float* grad_w, hipStream_t s);
 
 }  // namespace tetra

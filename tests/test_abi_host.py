@@ -69,7 +69,7 @@ def good():
     [
         ("n1", 0, -1), ("n2", -3, -1), ("n3", 0, -1), ("nb", 0, -1), ("norb", 0, -1), ("ne", 0, -1),
         ("de", 0.0, -1), ("de", -0.5, -1), ("de", float("nan"), -1), ("e0", float("inf"), -1),
-        ("e0", float("nan"), -1), ("norb", 17, -2), ("ne", 1 << 24, -1), ("n1", 1 << 28, -1),
+        ("e0", float("nan"), -1), ("norb", 17, -2), ("ne", (1 << 22) + 1, -1), ("n1", 1 << 28, -1),
     ],
 )
 def test_forward_rejects_bad_descriptors(L, field, value, status):

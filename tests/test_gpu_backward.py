@@ -203,3 +203,23 @@ def test_autograd_function_matches_backward(torch_dev):
     torch.cuda.synchronize()
     assert torch.allclose(eps.grad, ge, rtol=1e-5, atol=1e-6 * float(ge.abs().max()))
     assert torch.allclose(w.grad, gw, rtol=1e-5, atol=1e-6 * float(gw.abs().max()))
+
+
+def test_gradient_with_fp16_weights(torch_dev, oracle_lib):
+    """The adjoint of the FP16-weight forward: gradients with respect to the dequantised weights."""
+    torch, dev = torch_dev
+    import paper_1710_10789_amd as tetra
+
+    grid = (9, 6, 21)
+    eps, w = synth.band_structure(16, 6, grid)
+    e0, de = synth.energy_grid(eps, 120)
+    w16, scale = tetra.half_weights(torch.from_numpy(w))
+    deq = (w16.float() * scale[:, None, None]).numpy()
+    G = np.random.default_rng(4).normal(size=(120, 16)).astype(np.float32).astype(np.float64)
+    re, rw = oracle_lib.dos_backward(eps, deq, grid, e0, de, G)
+    ge, gw = tetra.dos_backward(torch.from_numpy(eps).to(dev), w16.to(dev), grid, e0, de,
+                                torch.from_numpy(G.astype(np.float32)).to(dev), w_scale=scale.to(dev))
+    torch.cuda.synchronize()
+    okw, _, _ = gate(gw.cpu().numpy(), rw)
+    oke, _, _ = gate(ge.cpu().numpy(), re)
+    assert okw and oke

@@ -124,3 +124,71 @@ def test_parity_64cube_8orb_1000E_full(torch_dev, oracle_lib):
     got, ref = _check(torch_dev, oracle_lib, eps, w, c["grid"], e0, de, c["ne"])
     again = _gpu_dos(torch_dev, eps, w, c["grid"], e0, de, c["ne"])
     assert _err(again, got) <= 1e-6
+
+
+def test_signed_weights_use_the_wide_accumulator(torch_dev, oracle_lib):
+    """Weights of both signs (a general observable in place of b): every bin's sum stays exact."""
+    grid = (6, 5, 20)
+    eps, w = synth.band_structure(3, 4, grid)
+    w = (w - 0.4).astype(np.float32)
+    e0, de = synth.energy_grid(eps, 180)
+    _check(torch_dev, oracle_lib, eps, w, grid, e0, de, 180)
+
+
+def test_nearly_flat_band(torch_dev, oracle_lib):
+    """Spans far below the energy step: point values spike, and the workgroup bound is dominated by
+    narrow tetrahedra."""
+    grid = (8, 6, 20)
+    rng = np.random.default_rng(3)
+    eps = (0.3 + 1e-4 * rng.standard_normal((2, 960))).astype(np.float32)
+    eps[1] += 0.2
+    w = rng.uniform(0, 1, (2, 4, 960)).astype(np.float32)
+    _check(torch_dev, oracle_lib, eps, w, grid, 0.25, 0.013, 30)
+
+
+def _fp16_inputs(w):
+    """Per-band power-of-two scale (exact), FP16 mantissa rounding: the precision variant's weights."""
+    import torch
+
+    import paper_1710_10789_amd as tetra
+
+    w16, scale = tetra.half_weights(torch.from_numpy(w))
+    deq = (w16.float() * scale[:, None, None]).numpy()
+    return w16, scale, deq
+
+
+def test_fp16_weights(torch_dev, oracle_lib):
+    torch, dev = torch_dev
+    import paper_1710_10789_amd as tetra
+
+    grid = (12, 10, 16)
+    eps, w = synth.band_structure(16, 5, grid)
+    e0, de = synth.energy_grid(eps, 400)
+    w16, scale, deq = _fp16_inputs(w)
+    got = tetra.dos_forward(torch.from_numpy(eps).to(dev), w16.to(dev), grid, e0, de, 400, w_scale=scale.to(dev))
+    torch.cuda.synchronize()
+    got = got.cpu().numpy().astype(np.float64)
+    ref32, _ = oracle_lib.dos(eps, w, grid, e0, de, 400)     # against the FP32 weights: FP16 gate
+    refdq, _ = oracle_lib.dos(eps, deq, grid, e0, de, 400)   # against the dequantised weights: FP32 gate
+    e32, edq = _err(got, ref32), _err(got, refdq)
+    print(f"[case] fp16 err vs fp32 weights {e32:.3e}, vs dequantised {edq:.3e}", flush=True)
+    assert e32 <= 1e-3 and edq <= TOL_F32
+
+
+@pytest.mark.parametrize("grid,norb,ne", [((16, 16, 16), 8, 200), ((5, 7, 3), 3, 150), ((9, 6, 21), 16, 3000)])
+def test_exact_accumulation_mode(torch_dev, oracle_lib, grid, norb, ne):
+    """TETRA_KAHAN: exact cross-workgroup sums; parity with the oracle and bitwise reproducibility."""
+    torch, dev = torch_dev
+    import paper_1710_10789_amd as tetra
+
+    eps, w = synth.band_structure(norb, 2, grid)
+    e0, de = synth.energy_grid(eps, ne)
+    te, tw = torch.from_numpy(eps).to(dev), torch.from_numpy(w).to(dev)
+    a = tetra.dos_forward(te, tw, grid, e0, de, ne, kahan=True)
+    b = tetra.dos_forward(te, tw, grid, e0, de, ne, kahan=True)
+    torch.cuda.synchronize()
+    ref, _ = oracle_lib.dos(eps, w, grid, e0, de, ne)
+    err = _err(a.cpu().numpy().astype(np.float64), ref)
+    print(f"[case] exact-mode err {err:.3e}", flush=True)
+    assert err <= TOL_F32
+    assert torch.equal(a, b)
