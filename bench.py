@@ -196,6 +196,139 @@ def summarize_profiles(kt_dir, fetch_dir=None, write_dir=None, copy_fetch_dir=No
     return text
 
 
+def _time_events(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(steps):
+        fn()
+    ev[1].record()
+    torch.cuda.synchronize()
+    return ev[0].elapsed_time(ev[1]) / steps
+
+
+def bench_precision(args, torch, tetra, dev):
+    """128^3 grid, 16 bands x 16 orbitals, 2000 energies: FP16 weights with a per-band scale and the
+    exact accumulation, against plain FP32; errors against the FP64 oracle."""
+    from paper_1710_10789_amd import tune
+
+    c = synth.config("k128_b16_e2000")
+    grid, norb, ne = c["grid"], c["norb"], c["ne"]
+    t0 = time.perf_counter()
+    eps_np, w_np = synth.band_structure(norb, c["seed"], grid, progress=True)
+    t_gen = time.perf_counter() - t0
+    e0, de = synth.energy_grid(eps_np, ne)
+    nb, nk = eps_np.shape
+    dense = 6 * nk * nb * ne
+    print(f"[precision] band structure ready ({t_gen:.1f} s)", file=sys.stderr, flush=True)
+    uwin = count_window_updates(eps_np, grid, e0, de, ne)
+    eps = torch.from_numpy(eps_np).to(dev)
+    w = torch.from_numpy(w_np).to(dev)
+    w16, scale = tetra.half_weights(w)
+    out = torch.empty((ne, norb), device=dev)
+    tile, _ = tune.tune_forward(eps, w16, grid, e0, de, ne, w_scale=scale, reps=2)
+    runs = {
+        "fp32": lambda: tetra.dos_forward(eps, w, grid, e0, de, ne, out=out, tile=tile),
+        "fp16": lambda: tetra.dos_forward(eps, w16, grid, e0, de, ne, w_scale=scale, out=out, tile=tile),
+        "fp16_exact": lambda: tetra.dos_forward(eps, w16, grid, e0, de, ne, w_scale=scale, out=out, kahan=True),
+        "fp32_exact": lambda: tetra.dos_forward(eps, w, grid, e0, de, ne, out=out, kahan=True),
+    }
+    print("[precision] timing", file=sys.stderr, flush=True)
+    ms = {k: _time_events(torch, f, args.steps, args.warmup) for k, f in runs.items()}
+    results = {}
+    for k, f in runs.items():
+        f()
+        torch.cuda.synchronize()
+        results[k] = out.cpu().numpy().astype(np.float64)
+    rec = {
+        "metric": "tetra-band-energy updates/s, precision variant (FP16 weights, exact accumulation)",
+        "value": dense / (ms["fp16_exact"] * 1e-3),
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms["fp16_exact"],
+        "higher_is_better": True,
+        "dtype": "f32 math, f16 weights",
+        "data": "synthetic (seeded random 16-orbital tight-binding model)",
+        "config": {"workload": "k128_b16_e2000: 128^3 periodic k-grid, 16 bands x 16 orbitals, 2000 energies",
+                   "dense_updates_per_pass": dense, "in_window_updates_per_pass": uwin,
+                   "tile": list(tetra.TILE_SHAPES[tile]), "host_eigh_s": t_gen},
+        "ms": ms,
+        "updates_per_s": {k: dense / (v * 1e-3) for k, v in ms.items()},
+        "hbm_gbs_algorithmic": {"fp32": (4 * nk * nb * (1 + norb)) / (ms["fp32"] * 1e-3) / 1e9,
+                                "fp16": (4 * nk * nb + 2 * nk * nb * norb) / (ms["fp16"] * 1e-3) / 1e9},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+
+        oracle.build()
+        cores = len(os.sched_getaffinity(0))
+        print(f"[precision] FP64 oracle on {cores} threads", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        ref, _ = oracle.dos(eps_np, w_np, grid, e0, de, ne, nthreads=cores)
+        t_or = time.perf_counter() - t0
+        scale_ref = np.abs(ref).max()
+        rec["error_vs_fp64_oracle"] = {k: float(np.abs(v - ref).max() / scale_ref) for k, v in results.items()}
+        rec["cpu_baseline"] = {"value": dense / t_or, "unit": "updates/s", "cores": cores, "kind": "oracle",
+                               "sample": f"the whole workload, one forward pass, FP64 ({t_or:.1f} s)"}
+    print(json.dumps(rec), flush=True)
+
+
+def bench_batched(args, torch, tetra, dev):
+    """32 independently seeded 8-orbital models, cubic grids from {24,32,48,64,96}^3 and 256..2048
+    energies, through one persistent launch captured in a HIP graph, tile shapes per problem from the
+    autotuner."""
+    from paper_1710_10789_amd import tune
+
+    specs = synth.batched_items()
+    probs, dense, uwin = [], 0, 0
+    t0 = time.perf_counter()
+    for seed, grid, ne in specs:
+        eps_np, w_np = synth.band_structure(8, seed, grid, progress=True)
+        e0, de = synth.energy_grid(eps_np, ne)
+        probs.append((torch.from_numpy(eps_np).to(dev), torch.from_numpy(w_np).to(dev), grid, e0, de, ne))
+        dense += 6 * eps_np.shape[1] * 8 * ne
+        uwin += count_window_updates(eps_np, grid, e0, de, ne)
+    t_gen = time.perf_counter() - t0
+    tiles = tune.tiles_for_batch(probs)
+    ws = torch.empty(tetra.batched_workspace_bytes(probs), dtype=torch.uint8, device=dev)
+    outs = [torch.empty((p[5], 8), device=dev) for p in probs]
+    tetra.dos_batched(probs, workspace=ws, out=outs, tiles=tiles)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            tetra.dos_batched(probs, workspace=ws, out=outs, tiles=tiles)
+    torch.cuda.current_stream().wait_stream(s)
+    ms_graph = _time_events(torch, g.replay, args.steps, args.warmup)
+    ms_eager = _time_events(torch, lambda: tetra.dos_batched(probs, workspace=ws, out=outs, tiles=tiles),
+                            args.steps, args.warmup)
+    ms_single = _time_events(torch, lambda: [tetra.dos_forward(*p, tile=t) for p, t in zip(probs, tiles)],
+                             args.steps, args.warmup)
+    print(json.dumps({
+        "metric": "tetra-band-energy updates/s, batched (32 models, one persistent graph-captured launch)",
+        "value": dense / (ms_graph * 1e-3),
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_graph,
+        "higher_is_better": True,
+        "dtype": "f32",
+        "data": "synthetic (32 seeded random 8-orbital tight-binding models)",
+        "config": {"workload": "batch32: grids from {24,32,48,64,96}^3, 256..2048 energies",
+                   "grids": [sp[1][0] for sp in specs], "energies": [sp[2] for sp in specs],
+                   "dense_updates_per_pass": dense, "in_window_updates_per_pass": uwin,
+                   "tiles": tiles, "host_eigh_s": t_gen},
+        "ms": {"graph": ms_graph, "eager_batched": ms_eager, "one_launch_per_model": ms_single},
+    }), flush=True)
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-profiles":
         ap = argparse.ArgumentParser()
@@ -221,6 +354,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--mode", choices=["fwdbwd", "fwd"], default="fwdbwd")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tiles", help="forward,backward tile shape ids (skips the autotuner)")
+    ap.add_argument("--workload", choices=["headline", "precision", "batched"], default="headline",
+                    help="headline: 64^3 x 8 x 8 x 1000 fwd+bwd (the metric); precision: 128^3 x 16 x 16 x 2000 "
+                         "with FP16 weights and exact accumulation; batched: 32 models, one persistent launch")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device-to-device copy of 256 MiB (5 times) to scale HBM byte counters")
     args = ap.parse_args()
@@ -244,6 +381,10 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 5}), flush=True)
         return
+    if args.workload == "precision":
+        return bench_precision(args, torch, tetra, dev)
+    if args.workload == "batched":
+        return bench_batched(args, torch, tetra, dev)
     c = synth.config(WORKLOAD)
     grid, norb, ne = c["grid"], c["norb"], c["ne"]
     eps_np, w_np = synth.band_structure(norb, c["seed"], grid)
@@ -266,17 +407,27 @@ def main():
     gw = torch.empty_like(w)
     torch.cuda.synchronize()
 
+    # tile shapes from the autotuner (outside the timed region)
+    from paper_1710_10789_amd import tune
+
+    if args.tiles:
+        tile_f, tile_b = (int(x) for x in args.tiles.split(","))
+        times_f = times_b = None
+    else:
+        tile_f, times_f = tune.tune_forward(eps, w, grid, e0, de, ne, reps=3)
+        tile_b, times_b = tune.tune_backward(eps, w, grid, e0, de, G, reps=3)
+
     stream = torch.cuda.current_stream(dev)
     use_bwd = args.mode == "fwdbwd"
 
     def step(ev=None):
         if ev is not None:
             ev[0].record(stream)
-        tetra.dos_forward(eps, w, grid, e0, de, ne, out=dos)
+        tetra.dos_forward(eps, w, grid, e0, de, ne, out=dos, tile=tile_f)
         if ev is not None:
             ev[1].record(stream)
         if use_bwd:
-            tetra.dos_backward(eps, w, grid, e0, de, G, grad_eps=ge, grad_w=gw)
+            tetra.dos_backward(eps, w, grid, e0, de, G, grad_eps=ge, grad_w=gw, tile=tile_b)
             if ev is not None:
                 ev[2].record(stream)
 
@@ -331,6 +482,8 @@ def main():
             "workload": f"{WORKLOAD}: 64^3 periodic k-grid, 8 bands x 8 orbitals, 1000 energies, FP32 SoA",
             "step": "forward + backward" if use_bwd else "forward",
             "n_tetrahedra": n_tet,
+            "tile_forward": list(tetra.TILE_SHAPES[tile_f]),
+            "tile_backward": list(tetra.TILE_SHAPES[tile_b]),
             "dense_updates_per_pass": dense,
             "in_window_updates_per_pass": uwin,
         },
@@ -346,6 +499,7 @@ def main():
         "roofline_bwd": ({"achieved": f_bwd / t_bwd / 1e12, "frac": f_bwd / t_bwd / 1e12 / PEAK_FP32_VALU_TFLOPS,
                           "hbm_gbs_algorithmic": b_bwd / t_bwd / 1e9} if use_bwd else None),
         "kernel_source_sha": {k: kernel_source_hash(k) for k in KERNEL_SOURCES},
+        "autotune_ms": {"forward": times_f, "backward": times_b},
     }
     if not args.no_cpu_baseline:
         def gpu_fn():

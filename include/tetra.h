@@ -68,8 +68,13 @@ enum {
    * library-owned device buffer of 256 + 8*ne*norb bytes, allocated on the first such call on a
    * device and kept until the process ends; such calls must not overlap on one device. The adjoint
    * sums at most eight partial values per output element and ignores the flag. */
-  TETRA_KAHAN = 1u
+  TETRA_KAHAN = 1u,
+  /* Bits 8..11 select the tile shape of the forward and adjoint kernels (0 = default); an autotuner
+   * picks it per problem class. Shapes are TX x TY x TZ cubes along grid axes (1, 2, 3):
+   * 0: 4x4x16, 1: 8x8x4, 2: 4x8x8, 3: 8x4x8, 4: 4x16x4, 5: 16x4x4. TETRA_KAHAN requires shape 0. */
+  TETRA_TILE_MASK = 0xF00u
 };
+#define TETRA_TILE(v) (((unsigned)(v) & 0xFu) << 8)
 
 /* Problem descriptor (host memory). */
 typedef struct {
@@ -117,6 +122,7 @@ typedef struct {
   const void* w;
   const float* w_scale;
   float* dos;
+  int tile; /* tile shape id as for TETRA_TILE (0 = default) */
 } tetra_item;
 
 /*

@@ -38,6 +38,17 @@ TETRA_W_F32 = 0
 TETRA_W_F16 = 1
 TETRA_KAHAN = 1
 MAX_NORB = 16
+# tile shapes (cubes along grid axes 1, 2, 3) selectable through the flags' bits 8..11
+TILE_SHAPES = ((4, 4, 16), (8, 8, 4), (4, 8, 8), (8, 4, 8), (4, 16, 4), (16, 4, 4))
+
+
+def _tile_flag(tile):
+    if tile is None:
+        return 0
+    t = int(tile)
+    if not 0 <= t < len(TILE_SHAPES):
+        raise ValueError(f"tile must be in 0..{len(TILE_SHAPES) - 1}")
+    return t << 8
 
 
 class TetraError(RuntimeError):
@@ -69,6 +80,7 @@ class TetraItem(ctypes.Structure):
         ("w", ctypes.c_void_p),
         ("w_scale", ctypes.c_void_p),
         ("dos", ctypes.c_void_p),
+        ("tile", ctypes.c_int),
     ]
 
 
@@ -159,11 +171,12 @@ def _shapes(eps, w, grid):
     return nk, nb, norb
 
 
-def dos_forward(eps, w, grid, e0, de, ne, *, w_scale=None, kahan=False, out=None):
+def dos_forward(eps, w, grid, e0, de, ne, *, w_scale=None, kahan=False, out=None, tile=None):
     """Orbital-resolved DOS ``[ne, norb]`` (FP32) on the current HIP stream.
 
     eps: float32 ``[nb, nk]``; w: float32 or float16 ``[nb, norb, nk]`` (float16 needs ``w_scale``
-    float32 ``[nb]``); grid: (n1, n2, n3) with nk = n1*n2*n3; E_j = e0 + j*de.
+    float32 ``[nb]``); grid: (n1, n2, n3) with nk = n1*n2*n3; E_j = e0 + j*de. ``kahan`` selects the
+    exact cross-workgroup accumulation; ``tile`` an index into ``TILE_SHAPES`` (default 0).
     """
     torch = _torch()
     nk, nb, norb = _shapes(eps, w, grid)
@@ -184,13 +197,13 @@ def dos_forward(eps, w, grid, e0, de, ne, *, w_scale=None, kahan=False, out=None
     st = lib().tetra_dos_forward(
         ctypes.byref(d), eps.data_ptr(), w.data_ptr(), wtype,
         w_scale.data_ptr() if w_scale is not None else None, out.data_ptr(),
-        TETRA_KAHAN if kahan else 0, _stream_handle(dev))
+        (TETRA_KAHAN if kahan else 0) | _tile_flag(tile), _stream_handle(dev))
     _check("tetra_dos_forward", st)
     return out
 
 
 def dos_backward(eps, w, grid, e0, de, grad_dos, *, w_scale=None, need_eps=True, need_w=True,
-                 grad_eps=None, grad_w=None):
+                 grad_eps=None, grad_w=None, tile=None):
     """``(dL/deps [nb, nk] or None, dL/dw [nb, norb, nk] float32 or None)`` for ``grad_dos = dL/dDOS``."""
     torch = _torch()
     nk, nb, norb = _shapes(eps, w, grid)
@@ -215,12 +228,12 @@ def dos_backward(eps, w, grid, e0, de, grad_dos, *, w_scale=None, need_eps=True,
         ctypes.byref(d), eps.data_ptr(), w.data_ptr(), wtype,
         w_scale.data_ptr() if w_scale is not None else None, grad_dos.data_ptr(),
         grad_eps.data_ptr() if grad_eps is not None else None,
-        grad_w.data_ptr() if grad_w is not None else None, 0, _stream_handle(dev))
+        grad_w.data_ptr() if grad_w is not None else None, _tile_flag(tile), _stream_handle(dev))
     _check("tetra_dos_backward", st)
     return grad_eps, grad_w
 
 
-def _batch_items(problems, out):
+def _batch_items(problems, out, tiles=None):
     torch = _torch()
     n = len(problems)
     items = (TetraItem * n)()
@@ -248,6 +261,7 @@ def _batch_items(problems, out):
         items[i].w = w.data_ptr()
         items[i].w_scale = w_scale.data_ptr() if w_scale is not None else None
         items[i].dos = o.data_ptr()
+        items[i].tile = 0 if tiles is None else _tile_flag(tiles[i]) >> 8
     return items, outs, wtype
 
 
@@ -257,26 +271,28 @@ def batched_workspace_bytes(problems) -> int:
     return int(lib().tetra_dos_batched_workspace(items, len(problems), wtype, 0))
 
 
-def dos_batched(problems, *, workspace=None, out=None):
+def dos_batched(problems, *, workspace=None, out=None, tiles=None):
     """DOS of many independent problems in one persistent launch per orbital count.
 
     problems: sequence of ``(eps, w, grid, e0, de, ne)`` or ``(eps, w, grid, e0, de, ne, w_scale)``
     with the same meaning as in :func:`dos_forward`. ``workspace`` is an optional uint8 device tensor
-    of at least :func:`batched_workspace_bytes` bytes (allocated here when omitted). Returns the list
-    of ``[ne, norb]`` results (``out`` if given).
+    of at least :func:`batched_workspace_bytes` bytes (allocated here when omitted). ``tiles`` gives
+    each problem's tile shape (see :mod:`paper_1710_10789_amd.tune`). Returns the list of
+    ``[ne, norb]`` results (``out`` if given).
     """
     torch = _torch()
     if len(problems) == 0:
         return []
-    items, outs, wtype = _batch_items(problems, out)
+    items, outs, wtype = _batch_items(problems, out, tiles)
     dev = problems[0][0].device
     need = int(lib().tetra_dos_batched_workspace(items, len(problems), wtype, 0))
     if need == 0:
         raise TetraError("tetra_dos_batched_workspace", -1)
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=dev)
-    if workspace.numel() < need or not workspace.is_cuda:
-        raise ValueError(f"workspace must be a device tensor of at least {need} bytes")
+    if not workspace.is_cuda or workspace.device != dev:
+        raise ValueError("workspace must be a tensor on the problems' device")
+    # the library checks the size (TETRA_ERR_WORKSPACE)
     st = lib().tetra_dos_batched(items, len(problems), wtype, 0, workspace.data_ptr(), workspace.numel(),
                                  _stream_handle(dev))
     _check("tetra_dos_batched", st)
@@ -288,18 +304,18 @@ def _autograd_function():
 
     class _TetraDOS(torch.autograd.Function):
         @staticmethod
-        def forward(ctx, eps, w, grid, e0, de, ne, kahan):
+        def forward(ctx, eps, w, grid, e0, de, ne, kahan, tiles):
             ctx.save_for_backward(eps, w)
-            ctx.args = (tuple(grid), float(e0), float(de))
-            return dos_forward(eps.contiguous(), w.contiguous(), grid, e0, de, ne, kahan=kahan)
+            ctx.args = (tuple(grid), float(e0), float(de), tiles[1])
+            return dos_forward(eps.contiguous(), w.contiguous(), grid, e0, de, ne, kahan=kahan, tile=tiles[0])
 
         @staticmethod
         def backward(ctx, g):
             eps, w = ctx.saved_tensors
-            grid, e0, de = ctx.args
+            grid, e0, de, btile = ctx.args
             ge, gw = dos_backward(eps.contiguous(), w.contiguous(), grid, e0, de, g.contiguous(),
-                                  need_eps=ctx.needs_input_grad[0], need_w=ctx.needs_input_grad[1])
-            return ge, gw, None, None, None, None, None
+                                  need_eps=ctx.needs_input_grad[0], need_w=ctx.needs_input_grad[1], tile=btile)
+            return ge, gw, None, None, None, None, None, None
 
     return _TetraDOS
 
@@ -307,7 +323,7 @@ def _autograd_function():
 _FN = None
 
 
-def dos(eps, w, grid, e0, de, ne, kahan=False):
+def dos(eps, w, grid, e0, de, ne, kahan=False, tile=None, backward_tile=None):
     """Differentiable orbital-resolved DOS ``[ne, norb]`` (FP32 weights).
 
     Gradients with respect to ``eps`` and ``w`` come from the adjoint kernel.
@@ -315,7 +331,7 @@ def dos(eps, w, grid, e0, de, ne, kahan=False):
     global _FN
     if _FN is None:
         _FN = _autograd_function()
-    return _FN.apply(eps, w, tuple(grid), e0, de, ne, kahan)
+    return _FN.apply(eps, w, tuple(grid), e0, de, ne, kahan, (tile, backward_tile))
 
 
 def from_eigh(evals, evecs):

@@ -1,10 +1,15 @@
-"""Build ``libtetra.so`` (the C-ABI library) in-tree with hipcc for gfx950."""
+"""Build ``libtetra.so`` (the C-ABI library) in-tree with hipcc for gfx950.
+
+Each HIP source is compiled to an object in parallel, then the objects are linked.
+"""
 from __future__ import annotations
 
 import glob
 import os
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -19,7 +24,6 @@ FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     "-munsafe-fp-atomics",
     # packed FP32 instructions stay disabled in every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -31,17 +35,29 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
-def build(extra_flags=(), verbose: bool = False) -> str:
-    """Compile every HIP source into ``paper_1710_10789_amd/libtetra.so``; returns its path."""
-    tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [HIPCC, *FLAGS, *extra_flags, "-I", INCLUDE, "-I", CSRC, *sources(), "-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError(f"hipcc failed ({res.returncode})")
-    os.replace(tmp, LIB)
+        raise RuntimeError(f"hipcc failed ({res.returncode}): {' '.join(cmd[-3:])}")
+
+
+def build(extra_flags=(), verbose: bool = False) -> str:
+    """Compile every HIP source into ``paper_1710_10789_amd/libtetra.so``; returns its path."""
+    with tempfile.TemporaryDirectory(prefix="tetra_build_") as tmpdir:
+        objs = []
+        cmds = []
+        for src in sources():
+            obj = os.path.join(tmpdir, os.path.basename(src) + ".o")
+            objs.append(obj)
+            cmds.append([HIPCC, *FLAGS, *extra_flags, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj])
+        with ThreadPoolExecutor(max_workers=min(len(cmds), max(1, os.cpu_count() or 1))) as ex:
+            list(ex.map(lambda c: _run(c, verbose), cmds))
+        tmp = LIB + f".tmp{os.getpid()}"
+        _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
+        os.replace(tmp, LIB)
     return LIB
 
 

@@ -82,14 +82,17 @@ tetra_status tetra_dos_forward(const tetra_desc* d, const float* eps, const void
   if (st != TETRA_OK) return st;
   if (!eps || !w || !dos) return TETRA_ERR_ARG;
   if ((st = check_weights(wtype, w_scale)) != TETRA_OK) return st;
-  if (flags & ~(unsigned)TETRA_KAHAN) return TETRA_ERR_ARG;
+  if (flags & ~(unsigned)(TETRA_KAHAN | TETRA_TILE_MASK)) return TETRA_ERR_ARG;
+  const int shape = (int)((flags & TETRA_TILE_MASK) >> 8);
+  if (shape >= tetra::kTileShapes) return TETRA_ERR_ARG;
+  if ((flags & TETRA_KAHAN) && shape != 0) return TETRA_ERR_UNSUPPORTED;
   void* scratch = nullptr;
   if (flags & TETRA_KAHAN) {
     const hipError_t e = exact_scratch(tetra::forward_exact_scratch_bytes(*d), &scratch);
     if (e != hipSuccess) return hip_status(e);
   }
   return hip_status(
-      tetra::forward(*d, eps, w, wtype == TETRA_W_F16 ? w_scale : nullptr, dos, scratch, (hipStream_t)stream));
+      tetra::forward(*d, eps, w, wtype == TETRA_W_F16 ? w_scale : nullptr, dos, scratch, shape, (hipStream_t)stream));
 }
 
 tetra_status tetra_dos_backward(const tetra_desc* d, const float* eps, const void* w, int wtype,
@@ -99,9 +102,11 @@ tetra_status tetra_dos_backward(const tetra_desc* d, const float* eps, const voi
   if (st != TETRA_OK) return st;
   if (!eps || !w || !grad_dos || (!grad_eps && !grad_w)) return TETRA_ERR_ARG;
   if ((st = check_weights(wtype, w_scale)) != TETRA_OK) return st;
-  if (flags & ~(unsigned)TETRA_KAHAN) return TETRA_ERR_ARG;
+  if (flags & ~(unsigned)(TETRA_KAHAN | TETRA_TILE_MASK)) return TETRA_ERR_ARG;
+  const int shape = (int)((flags & TETRA_TILE_MASK) >> 8);
+  if (shape >= tetra::kTileShapes) return TETRA_ERR_ARG;
   return hip_status(tetra::backward(*d, eps, w, wtype == TETRA_W_F16 ? w_scale : nullptr, grad_dos, grad_eps,
-                                    grad_w, (hipStream_t)stream));
+                                    grad_w, shape, (hipStream_t)stream));
 }
 
 size_t tetra_dos_batched_workspace(const tetra_item* items, int n, int wtype, unsigned flags) {
@@ -122,10 +127,13 @@ tetra_status tetra_dos_batched(const tetra_item* items, int n, int wtype, unsign
     if (st != TETRA_OK) return st;
     if (!it.eps || !it.w || !it.dos) return TETRA_ERR_ARG;
     if (check_weights(wtype, it.w_scale) != TETRA_OK) return TETRA_ERR_ARG;
+    if (it.tile < 0 || it.tile >= tetra::kTileShapes) return TETRA_ERR_ARG;
   }
   if (flags & TETRA_KAHAN) return TETRA_ERR_UNSUPPORTED;
   if (!workspace || ws_bytes < 256 * tetra::batched_launches(items, n)) return TETRA_ERR_WORKSPACE;
-  return hip_status(tetra::batched(items, n, wtype == TETRA_W_F16, workspace, (hipStream_t)stream));
+  std::vector<int> shapes(n);
+  for (int i = 0; i < n; ++i) shapes[i] = items[i].tile;
+  return hip_status(tetra::batched(items, shapes.data(), n, wtype == TETRA_W_F16, workspace, (hipStream_t)stream));
 }
 
 const char* tetra_status_string(int status) {

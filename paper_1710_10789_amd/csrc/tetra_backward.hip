@@ -25,10 +25,8 @@ namespace tetra {
 
 namespace {
 
-constexpr int TX = 4, TY = 4, TZ = 16;  // cubes per tile along grid axes 1, 2, 3
-constexpr int NT = TX * TY * TZ;        // one lane per cube
-constexpr int PX = TX + 1, PY = TY + 1, PZ = TZ + 1;
-constexpr int NP = PX * PY * PZ;  // grid points (cube corners) of the tile
+constexpr int NT = kTileCubes;      // one lane per cube of the tile
+constexpr int NPMAX = kTilePointsMax;  // grid points (cube corners) of the largest tile shape
 constexpr int HCAP = 4096;        // LDS capacity for the rows of G, in floats
 constexpr int NXCD = 8;
 
@@ -41,6 +39,7 @@ struct BwdArgs {
   float* grad_w;
   int n1, n2, n3, ne;
   float e0, de, inv_de, V;
+  int TX, TY, TZ;  // cubes per tile along grid axes 1, 2, 3 (TX*TY*TZ = NT)
   int t1, t2, t3;
   int ntiles, nunits, per_xcd;
 };
@@ -63,15 +62,18 @@ __device__ __forceinline__ float wave_max(float v) {
 template <int NORB, typename WT>
 __global__ __launch_bounds__(NT) void dos_backward_kernel(BwdArgs a) {
   constexpr int LC = HCAP / NORB;
-  __shared__ float s_eps[NP];
-  __shared__ float s_w[NP * NORB];
-  __shared__ float s_pt[NP * (NORB + 1)];  // per tile point: dL/deps, then dL/db[0..NORB)
+  __shared__ float s_eps[NPMAX];
+  __shared__ float s_w[NPMAX * NORB];
+  __shared__ float s_pt[NPMAX * (NORB + 1)];  // per tile point: dL/deps, then dL/db[0..NORB)
   __shared__ float s_G[HCAP];
   __shared__ float s_red[2 * (NT / 64)];
 
   const int b = blockIdx.x;
   const int unit = (b % NXCD) * a.per_xcd + b / NXCD;
   if (unit >= a.nunits) return;
+  const int TX = a.TX, TY = a.TY, TZ = a.TZ;
+  const int PY = TY + 1, PZ = TZ + 1;
+  const int NP = (TX + 1) * PY * PZ;
   const int band = unit / a.ntiles;
   const int tile = unit - band * a.ntiles;
   const int tz = tile % a.t3;
@@ -118,7 +120,7 @@ __global__ __launch_bounds__(NT) void dos_backward_kernel(BwdArgs a) {
   const int cz = tid % TZ, cy = (tid / TZ) % TY, cx = tid / (TZ * TY);
   const bool active = (x0 + cx < a.n1) && (y0 + cy < a.n2) && (z0 + cz < a.n3);
   const int pbase = (cx * PY + cy) * PZ + cz;
-  auto point_offset = [](int s) { return (s & 1) * (PY * PZ) + ((s >> 1) & 1) * PZ + (s >> 2); };
+  auto point_offset = [PY, PZ](int s) { return (s & 1) * (PY * PZ) + ((s >> 1) & 1) * PZ + (s >> 2); };
 
   for (int c0 = J0; c0 <= J1; c0 += LC) {
     const int c1 = min(c0 + LC - 1, J1);
@@ -263,7 +265,7 @@ hipError_t launch_bwd(const BwdArgs& a, int grid, hipStream_t s) {
 }  // namespace
 
 hipError_t backward(const tetra_desc& d, const float* eps, const void* w, const float* w_scale, const float* G,
-                    float* grad_eps, float* grad_w, hipStream_t s) {
+                    float* grad_eps, float* grad_w, int shape, hipStream_t s) {
   BwdArgs a;
   a.eps = eps;
   a.w = w;
@@ -279,9 +281,13 @@ hipError_t backward(const tetra_desc& d, const float* eps, const void* w, const 
   a.de = d.de;
   a.inv_de = 1.0f / d.de;
   a.V = (float)(1.0 / (24.0 * (double)d.n1 * d.n2 * d.n3));
-  a.t1 = (d.n1 + TX - 1) / TX;
-  a.t2 = (d.n2 + TY - 1) / TY;
-  a.t3 = (d.n3 + TZ - 1) / TZ;
+  const TileShape sh = tile_shape(shape);
+  a.TX = sh.x;
+  a.TY = sh.y;
+  a.TZ = sh.z;
+  a.t1 = (d.n1 + sh.x - 1) / sh.x;
+  a.t2 = (d.n2 + sh.y - 1) / sh.y;
+  a.t3 = (d.n3 + sh.z - 1) / sh.z;
   a.ntiles = a.t1 * a.t2 * a.t3;
   a.nunits = a.ntiles * d.nb;
   a.per_xcd = (a.nunits + NXCD - 1) / NXCD;

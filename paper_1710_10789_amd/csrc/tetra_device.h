@@ -65,6 +65,15 @@ __host__ __device__ __forceinline__ void sort4(float e[4], int s[4]) {
   cswap(e[1], s[1], e[2], s[2]);
 }
 
+// 1/x by the hardware reciprocal (within 1 ulp; +inf for +0) on the device, a division on the host.
+__host__ __device__ __forceinline__ float rcp(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
+#endif
+}
+
 // a + b = hi + lo exactly (Knuth's two-sum).
 __host__ __device__ __forceinline__ void two_sum(float a, float b, float& hi, float& lo) {
   hi = a + b;
@@ -90,12 +99,12 @@ __host__ __device__ __forceinline__ TetSetup tet_setup(const float e[4], float e
   c.e41 = e[3] - e[0];
   const float e32 = e[2] - e[1], e42 = e[3] - e[1], e43 = e[3] - e[2];
   // Reciprocals of zero differences are infinite; the case that would use them is never selected.
-  c.r21 = 1.0f / c.e21;
-  c.r31 = 1.0f / c.e31;
-  c.r41 = 1.0f / c.e41;
-  c.r32 = 1.0f / e32;
-  c.r42 = 1.0f / e42;
-  c.r43 = 1.0f / e43;
+  c.r21 = rcp(c.e21);
+  c.r31 = rcp(c.e31);
+  c.r41 = rcp(c.e41);
+  c.r32 = rcp(e32);
+  c.r42 = rcp(e42);
+  c.r43 = rcp(e43);
   c.kA = V * c.r21 * c.r31 * c.r41;
   c.sA = c.r21 + c.r31 + c.r41;
   c.kC = V * c.r41 * c.r42 * c.r43;

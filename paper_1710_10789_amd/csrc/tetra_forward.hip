@@ -36,12 +36,9 @@ namespace tetra {
 
 namespace {
 
-constexpr int TX = 4, TY = 4, TZ = 16;  // cubes per tile along grid axes 1, 2, 3
-constexpr int NT = TX * TY * TZ;        // one lane per cube
-constexpr int PX = TX + 1, PY = TY + 1, PZ = TZ + 1;
-constexpr int NP = PX * PY * PZ;  // staged grid points (cube corners of the tile)
+constexpr int NT = kTileCubes;      // one lane per cube of the tile
+constexpr int NPMAX = kTilePointsMax;  // staged grid points (cube corners) of the largest tile shape
 constexpr int HCAP = 2048;        // LDS histogram capacity in 64-bit words
-constexpr int CP = 1;             // histogram copies (lane % CP picks one) to spread same-bin atomics
 constexpr int NXCD = 8;
 
 struct FwdArgs {
@@ -53,6 +50,7 @@ struct FwdArgs {
   unsigned long long* gacc;     // exact mode: [ne][norb] 64-bit fixed-point sums (mode 2)
   int n1, n2, n3, ne;
   float e0, de, inv_de, V;
+  int TX, TY, TZ;  // cubes per tile along grid axes 1, 2, 3 (TX*TY*TZ = NT)
   int t1, t2, t3;  // tiles along each axis
   int ntiles, nunits, per_xcd;
 };
@@ -84,12 +82,16 @@ __device__ __forceinline__ float wave_sum(float v) {
 // 2: DOS in the common scale fixed by *gbound, summed exactly into gacc with 64-bit global atomics.
 template <int NORB, typename WT, int MODE>
 __device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
-  constexpr int LC = ((HCAP / (NORB * CP)) - 1) & ~1;  // energies per histogram pass (even)
-  __shared__ float s_eps[NP];
-  __shared__ float s_w[NP * NORB];
+  constexpr int LC = ((HCAP / NORB) - 1) & ~1;  // energies per histogram pass (even)
+  constexpr int PITCH = LC + 1;  // odd row pitch: the flush reads across orbitals without bank conflicts
+  __shared__ float s_eps[NPMAX];
+  __shared__ float s_w[NPMAX * NORB];
   __shared__ unsigned long long s_hist[HCAP];
   __shared__ float s_red[4 * (NT / 64)];
 
+  const int TX = a.TX, TY = a.TY, TZ = a.TZ;
+  const int PY = TY + 1, PZ = TZ + 1;
+  const int NP = (TX + 1) * PY * PZ;
   const int band = unit / a.ntiles;
   const int tile = unit - band * a.ntiles;
   const int tz = tile % a.t3;
@@ -148,10 +150,11 @@ __device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
   const int cz = tid % TZ, cy = (tid / TZ) % TY, cx = tid / (TZ * TY);
   const bool valid = (x0 + cx < a.n1) && (y0 + cy < a.n2) && (z0 + cz < a.n3);
   const int pbase = (cx * PY + cy) * PZ + cz;
-  auto point_offset = [](int s) { return (s & 1) * (PY * PZ) + ((s >> 1) & 1) * PZ + (s >> 2); };
+  auto point_offset = [PY, PZ](int s) { return (s & 1) * (PY * PZ) + ((s >> 1) & 1) * PZ + (s >> 2); };
 
   // Bound on any bin's sum: sum over tetrahedra with a possibly non-empty window of 12 V bmax / E41.
   float bound = 0.0f, narrow = 0.0f;
+  const float c12 = 12.0f * a.V * bmax;
   if (MODE != 2 && valid) {
 #pragma unroll 1
     for (int t = 0; t < 6; ++t) {
@@ -169,7 +172,7 @@ __device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
       int jlo, jhi;
       energy_window(lo, hi, a.e0, a.inv_de, J0, J1, jlo, jhi);
       if (jlo > jhi + 2) continue;
-      const float term = 12.0f * a.V * bmax / (hi - lo);
+      const float term = c12 * rcp(hi - lo);
       bound += term;
       if (hi - lo < 2.0f * a.de) narrow += term;
     }
@@ -202,13 +205,18 @@ __device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
   const int sexp = min((packed ? 30 : 62) - bexp, 126);
   const float S = ldexpf(1.0f, sexp);  // B * S <= 2^30 (packed) or 2^62
   const double inv_S = ldexp(1.0, -sexp);
-  const int cp = tid % CP;
+  // Fold the power-of-two scale into the staged weights (exact): every deposit is then an integer-valued
+  // float without a per-orbital multiply.
+  for (int q = tid; q < NP * NORB; q += NT) s_w[q] *= S;
+  __syncthreads();
 
   for (int c0 = J0; c0 <= J1; c0 += LC) {
     const int c1 = min(c0 + LC - 1, J1);
     const int L = c1 - c0 + 1;
-    const int LP = L | 1;  // odd row pitch: the flush reads across orbitals without bank conflicts
-    for (int q = tid; q < rows * LP * CP; q += NT) s_hist[q] = 0ull;
+    for (int q = tid; q < rows * L; q += NT) {
+      const int r = q / L;
+      s_hist[r * PITCH + (q - r * L)] = 0ull;
+    }
     __syncthreads();
     if (valid) {
 #pragma unroll 1
@@ -240,41 +248,54 @@ __device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
         // a wavefront do not execute the other cases' code.
         int jA, jB;
         case_split(cs, a.de, a.inv_de, jlo, jhi, jA, jB);
+        // Packed: two orbitals per 64-bit word as unsigned 32-bit fields; every term is non-negative
+        // (the weights are, and the corner weights are clamped at zero against rounding), so the
+        // truncating conversion of 0.5 + v rounds v to the nearest integer (halves up).
         auto deposit = [&](int j, const float g[4]) {
-          unsigned long long* h = &s_hist[(j - c0) * CP + cp];
+          unsigned long long* h = &s_hist[j - c0];
           if (packed) {
 #pragma unroll
             for (int pr = 0; pr < NPAIR; ++pr) {
               const int m0 = 2 * pr, m1 = 2 * pr + 1;
-              const float v0 = g[0] * bb[0][m0] + g[1] * bb[1][m0] + g[2] * bb[2][m0] + g[3] * bb[3][m0];
-              unsigned long long word = (unsigned long long)__float2uint_rn(v0 * S);
+              float v0 = __builtin_fmaf(g[0], bb[0][m0], 0.5f);
+              v0 = __builtin_fmaf(g[1], bb[1][m0], v0);
+              v0 = __builtin_fmaf(g[2], bb[2][m0], v0);
+              v0 = __builtin_fmaf(g[3], bb[3][m0], v0);
+              unsigned long long word = (unsigned long long)(unsigned)v0;
               if (m1 < NORB) {
-                const float v1 = g[0] * bb[0][m1] + g[1] * bb[1][m1] + g[2] * bb[2][m1] + g[3] * bb[3][m1];
-                word |= (unsigned long long)__float2uint_rn(v1 * S) << 32;
+                float v1 = __builtin_fmaf(g[0], bb[0][m1], 0.5f);
+                v1 = __builtin_fmaf(g[1], bb[1][m1], v1);
+                v1 = __builtin_fmaf(g[2], bb[2][m1], v1);
+                v1 = __builtin_fmaf(g[3], bb[3][m1], v1);
+                word |= (unsigned long long)(unsigned)v1 << 32;
               }
-              atomicAdd(&h[pr * LP * CP], word);
+              atomicAdd(&h[pr * PITCH], word);
             }
           } else {
 #pragma unroll
             for (int m = 0; m < NORB; ++m) {
               const float v = g[0] * bb[0][m] + g[1] * bb[1][m] + g[2] * bb[2][m] + g[3] * bb[3][m];
-              atomicAdd(&h[m * LP * CP], (unsigned long long)__float2ll_rn(v * S));
+              atomicAdd(&h[m * PITCH], (unsigned long long)__float2ll_rn(v));
             }
           }
         };
         for (int j = jlo; j <= jA; ++j) {
           float g[4];
           corner_dos_A(cs, local_x(cs, j, a.de), g);
+          g[0] = fmaxf(g[0], 0.0f);  // g[1..3] are products of non-negative factors
           deposit(j, g);
         }
         for (int j = jA + 1; j <= jB; ++j) {
           float g[4];
           corner_dos_B(cs, local_x(cs, j, a.de), g);
+#pragma unroll
+          for (int l = 0; l < 4; ++l) g[l] = fmaxf(g[l], 0.0f);
           deposit(j, g);
         }
         for (int j = jB + 1; j <= jhi; ++j) {
           float g[4];
           corner_dos_C(cs, local_x(cs, j, a.de), g);
+          g[3] = fmaxf(g[3], 0.0f);
           deposit(j, g);
         }
       }
@@ -283,21 +304,12 @@ __device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
     for (int q = tid; q < L * NORB; q += NT) {
       const int r = q / NORB, m = q - r * NORB;
       const int row = packed ? (m >> 1) : m;
-      double sum = 0.0;
-#pragma unroll
-      for (int c = 0; c < CP; ++c) {
-        const unsigned long long w = s_hist[(row * LP + r) * CP + c];
-        if (packed) sum += (double)(unsigned)((m & 1) ? (w >> 32) : (w & 0xffffffffull));
-        else sum += (double)(long long)w;
-      }
+      const unsigned long long w = s_hist[row * PITCH + r];
       if (MODE == 2) {
-        const unsigned long long w = s_hist[(row * LP + r) * CP];
-        unsigned long long tot = w;
-#pragma unroll
-        for (int c = 1; c < CP; ++c) tot += s_hist[(row * LP + r) * CP + c];
-        if (tot != 0ull) atomicAdd(&a.gacc[(int64_t)(c0 + r) * NORB + m], tot);
-      } else if (sum != 0.0) {
-        atomic_add_global(&a.dos[(int64_t)(c0 + r) * NORB + m], (float)(sum * inv_S));
+        if (w != 0ull) atomicAdd(&a.gacc[(int64_t)(c0 + r) * NORB + m], w);
+      } else {
+        const double sum = packed ? (double)(unsigned)((m & 1) ? (w >> 32) : (w & 0xffffffffull)) : (double)(long long)w;
+        if (sum != 0.0) atomic_add_global(&a.dos[(int64_t)(c0 + r) * NORB + m], (float)(sum * inv_S));
       }
     }
     __syncthreads();
@@ -330,6 +342,7 @@ struct BatchItem {
   float* dos;
   int n1, n2, n3, ne;
   float e0, de;
+  int TX, TY, TZ;
   int t1, t2, t3, ntiles;
   int unit_begin;  // first global unit of this item (items in order, units band-major)
 };
@@ -367,6 +380,9 @@ __global__ __launch_bounds__(NT) void dos_batched_kernel(BatchArgs b) {
     a.de = it.de;
     a.inv_de = 1.0f / it.de;
     a.V = (float)(1.0 / (24.0 * (double)it.n1 * it.n2 * it.n3));
+    a.TX = it.TX;
+    a.TY = it.TY;
+    a.TZ = it.TZ;
     a.t1 = it.t1;
     a.t2 = it.t2;
     a.t3 = it.t3;
@@ -463,7 +479,7 @@ hipError_t fill_zero(float* p, int64_t n, hipStream_t s) {
 }
 
 hipError_t forward(const tetra_desc& d, const float* eps, const void* w, const float* w_scale, float* dos,
-                   void* exact_scratch, hipStream_t s) {
+                   void* exact_scratch, int shape, hipStream_t s) {
   FwdArgs a;
   // exact_scratch (exact mode): 256 bytes holding the bound, then ne*norb 64-bit sums
   a.gbound = exact_scratch ? static_cast<float*>(exact_scratch) : nullptr;
@@ -480,9 +496,13 @@ hipError_t forward(const tetra_desc& d, const float* eps, const void* w, const f
   a.de = d.de;
   a.inv_de = 1.0f / d.de;
   a.V = (float)(1.0 / (24.0 * (double)d.n1 * d.n2 * d.n3));  // V_T / (4 V_G)
-  a.t1 = (d.n1 + TX - 1) / TX;
-  a.t2 = (d.n2 + TY - 1) / TY;
-  a.t3 = (d.n3 + TZ - 1) / TZ;
+  const TileShape sh = tile_shape(shape);
+  a.TX = sh.x;
+  a.TY = sh.y;
+  a.TZ = sh.z;
+  a.t1 = (d.n1 + sh.x - 1) / sh.x;
+  a.t2 = (d.n2 + sh.y - 1) / sh.y;
+  a.t3 = (d.n3 + sh.z - 1) / sh.z;
   a.ntiles = a.t1 * a.t2 * a.t3;
   a.nunits = a.ntiles * d.nb;
   a.per_xcd = (a.nunits + NXCD - 1) / NXCD;
@@ -522,7 +542,7 @@ size_t batched_launches(const tetra_item* items, int n) {
   return launches;
 }
 
-hipError_t batched(const tetra_item* items, int n, bool half, void* workspace, hipStream_t s) {
+hipError_t batched(const tetra_item* items, const int* shapes, int n, bool half, void* workspace, hipStream_t s) {
   unsigned* counters = static_cast<unsigned*>(workspace);
   int launch = 0;
   for (int norb = 1; norb <= 16; ++norb) {
@@ -564,9 +584,13 @@ hipError_t batched(const tetra_item* items, int n, bool half, void* workspace, h
       it.ne = d.ne;
       it.e0 = d.e0;
       it.de = d.de;
-      it.t1 = (d.n1 + TX - 1) / TX;
-      it.t2 = (d.n2 + TY - 1) / TY;
-      it.t3 = (d.n3 + TZ - 1) / TZ;
+      const TileShape sh = tile_shape(shapes ? shapes[i] : 0);
+      it.TX = sh.x;
+      it.TY = sh.y;
+      it.TZ = sh.z;
+      it.t1 = (d.n1 + sh.x - 1) / sh.x;
+      it.t2 = (d.n2 + sh.y - 1) / sh.y;
+      it.t3 = (d.n3 + sh.z - 1) / sh.z;
       it.ntiles = it.t1 * it.t2 * it.t3;
       it.unit_begin = b.total;
       b.total += it.ntiles * d.nb;

@@ -10,17 +10,32 @@ namespace tetra {
 
 constexpr int kMaxBatch = 32;  // problems per persistent batched launch
 
+// Tile shapes (cubes along grid axes 1, 2, 3) of the forward and adjoint kernels: one lane per cube,
+// kTileCubes lanes per workgroup. Shape 0 is the default; the others are for the autotuner.
+constexpr int kTileCubes = 256;
+constexpr int kTileShapes = 6;
+struct TileShape {
+  int x, y, z;
+};
+// Every shape stages at most 425 points, the default's count, so LDS use (and occupancy) matches
+// the default.
+constexpr TileShape kTileShape[kTileShapes] = {{4, 4, 16}, {8, 8, 4}, {4, 8, 8}, {8, 4, 8}, {4, 16, 4}, {16, 4, 4}};
+constexpr int kTilePointsMax = 5 * 5 * 17;  // largest (x+1)(y+1)(z+1) above
+__host__ __device__ inline TileShape tile_shape(int id) {
+  return (id >= 0 && id < kTileShapes) ? kTileShape[id] : kTileShape[0];
+}
+
 hipError_t fill_zero(float* p, int64_t n, hipStream_t s);
 // w is float, or _Float16 when w_scale (per-band scale) is non-null. exact_scratch (or null) is device
 // memory of forward_exact_scratch_bytes(d) for the exact cross-workgroup accumulation.
 hipError_t forward(const tetra_desc& d, const float* eps, const void* w, const float* w_scale, float* dos,
-                   void* exact_scratch, hipStream_t s);
+                   void* exact_scratch, int shape, hipStream_t s);
 // Batched forward: items grouped by orbital count, up to kMaxBatch per persistent launch. The
 // workspace holds one 256-byte work counter per launch.
 size_t batched_launches(const tetra_item* items, int n);
-hipError_t batched(const tetra_item* items, int n, bool half, void* workspace, hipStream_t s);
+hipError_t batched(const tetra_item* items, const int* shapes, int n, bool half, void* workspace, hipStream_t s);
 inline size_t forward_exact_scratch_bytes(const tetra_desc& d) { return 256 + 8 * (size_t)d.ne * d.norb; }
 hipError_t backward(const tetra_desc& d, const float* eps, const void* w, const float* w_scale, const float* G,
-                    float* grad_eps, float* grad_w, hipStream_t s);
+                    float* grad_eps, float* grad_w, int shape, hipStream_t s);
 
 }  // namespace tetra

@@ -3,6 +3,8 @@ from __future__ import annotations
 
 import hashlib
 import os
+import sys
+import threading
 from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
@@ -58,11 +60,13 @@ def _cache_path(norb, seed, grid):
     return os.path.join(root, f"tb_{norb}o_s{seed}_{grid[0]}x{grid[1]}x{grid[2]}_{tag}.npz")
 
 
-def band_structure(norb: int, seed: int, grid, cache: bool = True, workers: int | None = None):
+def band_structure(norb: int, seed: int, grid, cache: bool = True, workers: int | None = None,
+                   progress: bool = False):
     """Return ``(eps, w)``: FP32 ``eps[nb][nk]`` and ``w[nb][norb][nk]`` (nb == norb) of the seeded model.
 
     The diagonalisation runs on the host (numpy ``eigh`` in complex128), chunked over threads, and is
-    cached as ``.npz`` because it dominates set-up time for large grids.
+    cached as ``.npz`` because it dominates set-up time for large grids. ``progress`` prints a line to
+    stderr after every tenth of the chunks.
     """
     grid = tuple(int(x) for x in grid)
     path = _cache_path(norb, seed, grid)
@@ -78,11 +82,20 @@ def band_structure(norb: int, seed: int, grid, cache: bool = True, workers: int 
     if workers is None:
         workers = max(1, min(16, len(os.sched_getaffinity(0))))
 
+    done = [0]
+    lock = threading.Lock()
+
     def run(b):
         lo, hi = b
         ev, bw = _diag_chunk(hops, grid, lo, hi)
         eps[:, lo:hi] = ev.T.astype(np.float32)
         w[:, :, lo:hi] = bw.transpose(2, 1, 0).astype(np.float32)
+        if progress:
+            with lock:
+                done[0] += 1
+                if done[0] * 10 // len(bounds) != (done[0] - 1) * 10 // len(bounds):
+                    print(f"[synth] eigh {grid} norb {norb}: {done[0]}/{len(bounds)} chunks", file=sys.stderr,
+                          flush=True)
 
     if workers == 1 or len(bounds) == 1:
         for b in bounds:

@@ -90,6 +90,9 @@ def test_forward_rejects_bad_pointers_and_flags(L):
     d = good()
     d.e0, d.de, d.ne = 3.0e38, 1.0e37, 1000  # last grid energy overflows FP32
     assert _fwd(L, d) == -1
+    assert _fwd(L, good(), flags=7 << 8) == -1  # no such tile shape
+    assert _fwd(L, good(), flags=15 << 8) == -1
+    assert _fwd(L, good(), flags=1 | (2 << 8)) == -2  # exact mode only with the default tile
 
 
 def test_backward_rejects_bad_arguments(L):
@@ -99,9 +102,18 @@ def test_backward_rejects_bad_arguments(L):
     d.norb = 40
     assert _bwd(L, d) == -2
     assert _bwd(L, good(), flags=4) == -1
+    assert _bwd(L, good(), flags=9 << 8) == -1
 
 
 def test_batched_rejects_bad_arguments(L):
     assert L.tetra_dos_batched(None, 1, 0, 0, None, 0, None) == -1
     items = (tetra.TetraItem * 1)()
     assert L.tetra_dos_batched(items, 0, 0, 0, None, 0, None) == -1
+    items[0].d = good()
+    items[0].eps, items[0].w, items[0].dos = FAKE, FAKE, FAKE
+    items[0].tile = 6  # no such tile shape
+    assert L.tetra_dos_batched(items, 1, 0, 0, FAKE, 4096, None) == -1
+    items[0].tile = 0
+    assert L.tetra_dos_batched(items, 1, 0, 1, FAKE, 4096, None) == -2  # no exact mode in batches
+    assert L.tetra_dos_batched(items, 1, 0, 0, FAKE, 8, None) == -3  # workspace too small
+    assert L.tetra_dos_batched_workspace(items, 1, 0, 0) == 256

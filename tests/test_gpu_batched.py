@@ -127,3 +127,17 @@ def test_batched_graph_capture_replays(torch_dev):
         torch.cuda.synchronize()
         for o, e in zip(outs, eager):
             assert torch.allclose(o, e, rtol=1e-6, atol=1e-6 * float(e.abs().max())), rep
+
+
+def test_batched_per_item_tile_shapes(torch_dev, oracle_lib):
+    """Items of one persistent launch may use different tile shapes."""
+    torch, dev = torch_dev
+    import paper_1710_10789_amd as tetra
+
+    specs = [(60 + i, (5 + i, 7, 9 + 2 * i), 150 + 37 * i, 8) for i in range(6)]
+    probs, host = _problems(torch, dev, specs)
+    outs = tetra.dos_batched(probs, tiles=list(range(6)))
+    torch.cuda.synchronize()
+    for o, (eps, w, grid, e0, de, ne) in zip(outs, host):
+        ref, _ = oracle_lib.dos(eps, w, grid, e0, de, ne)
+        assert _err(o.cpu().numpy().astype(np.float64), ref) <= 1e-5

@@ -1,0 +1,76 @@
+"""GPU tests of the precision variant at a reduced size of the 128^3 x 16 x 16 x 2000 workload: FP16
+weights with a per-band power-of-two scale, exact (order-independent) accumulation, and the spread of
+repeated runs. All through the C ABI against the FP64 oracle.
+
+Gates (error = max |D - D_ref| / max |D_ref|): FP16 weights <= 1e-3 against the FP32 weights and <= 1e-5
+against the dequantised weights; exact mode <= 1e-5 and bitwise repeatable; plain FP32 repeated runs
+agree to <= 1e-6 (cross-workgroup float atomics make them differ only in rounding)."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+GRID = (32, 32, 32)
+NORB = 16
+NE = 2000
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def model(oracle_lib):
+    eps, w = synth.band_structure(NORB, 0, GRID)
+    e0, de = synth.energy_grid(eps, NE)
+    ref, _ = oracle_lib.dos(eps, w, GRID, e0, de, NE)
+    return eps, w, e0, de, ref
+
+
+def _err(got, ref):
+    return np.abs(got - ref).max() / np.abs(ref).max()
+
+
+def test_fp16_weights_exact_accumulation(torch_dev, oracle_lib, model):
+    torch, dev = torch_dev
+    import paper_1710_10789_amd as tetra
+
+    eps, w, e0, de, ref32 = model
+    w16, scale = tetra.half_weights(torch.from_numpy(w))
+    deq = (w16.float() * scale[:, None, None]).numpy()
+    refdq, _ = oracle_lib.dos(eps, deq, GRID, e0, de, NE)
+    te, w16d, sd = torch.from_numpy(eps).to(dev), w16.to(dev), scale.to(dev)
+    print(f"[case] {GRID} nb=norb={NORB} ne={NE} fp16 + exact", flush=True)
+    for kahan in (False, True):
+        got = tetra.dos_forward(te, w16d, GRID, e0, de, NE, w_scale=sd, kahan=kahan)
+        torch.cuda.synchronize()
+        got = got.cpu().numpy().astype(np.float64)
+        e32, edq = _err(got, ref32), _err(got, refdq)
+        print(f"[case] kahan={kahan}: err vs fp32 weights {e32:.3e}, vs dequantised {edq:.3e}", flush=True)
+        assert e32 <= 1e-3 and edq <= 1e-5
+
+
+def test_exact_fp32_and_repeat_spread(torch_dev, model):
+    torch, dev = torch_dev
+    import paper_1710_10789_amd as tetra
+
+    eps, w, e0, de, ref = model
+    te, tw = torch.from_numpy(eps).to(dev), torch.from_numpy(w).to(dev)
+    exact = [tetra.dos_forward(te, tw, GRID, e0, de, NE, kahan=True) for _ in range(3)]
+    plain = [tetra.dos_forward(te, tw, GRID, e0, de, NE) for _ in range(3)]
+    torch.cuda.synchronize()
+    assert all(torch.equal(exact[0], x) for x in exact[1:])
+    err = _err(exact[0].cpu().numpy().astype(np.float64), ref)
+    scale = float(plain[0].abs().max())
+    spread = max(float((x - plain[0]).abs().max()) for x in plain[1:]) / scale
+    print(f"[case] exact err {err:.3e}, plain repeat spread {spread:.3e}", flush=True)
+    assert err <= 1e-5
+    assert spread <= 1e-6
+    for x in plain:
+        assert _err(x.cpu().numpy().astype(np.float64), ref) <= 1e-5
