@@ -69,9 +69,14 @@ enum {
    * device and kept until the process ends; such calls must not overlap on one device. The adjoint
    * sums at most eight partial values per output element and ignores the flag. */
   TETRA_KAHAN = 1u,
+  /* Bitwise reproducible result. tetra_dos_forward takes the exact path of TETRA_KAHAN for it (same
+   * buffer, same result). tetra_dos_backward and tetra_dos_batched do not offer it: their sums across
+   * workgroups are float atomics (TETRA_ERR_UNSUPPORTED). */
+  TETRA_DETERMINISTIC = 2u,
   /* Bits 8..11 select the tile shape of the forward and adjoint kernels (0 = default); an autotuner
    * picks it per problem class. Shapes are TX x TY x TZ cubes along grid axes (1, 2, 3):
-   * 0: 4x4x16, 1: 8x8x4, 2: 4x8x8, 3: 8x4x8, 4: 4x16x4, 5: 16x4x4. TETRA_KAHAN requires shape 0. */
+   * 0: 4x4x16, 1: 8x8x4, 2: 4x8x8, 3: 8x4x8, 4: 4x16x4, 5: 16x4x4. TETRA_KAHAN and
+   * TETRA_DETERMINISTIC require shape 0. */
   TETRA_TILE_MASK = 0xF00u
 };
 #define TETRA_TILE(v) (((unsigned)(v) & 0xFu) << 8)
@@ -93,7 +98,7 @@ typedef struct {
  *   wtype    TETRA_W_F32 or TETRA_W_F16
  *   w_scale  device, float [nb]            per-band scale for TETRA_W_F16, else NULL
  *   dos      device, float [ne][norb]      result, overwritten
- *   flags    0 or TETRA_KAHAN
+ *   flags    TETRA_KAHAN, TETRA_DETERMINISTIC, TETRA_TILE(shape), or 0
  *   stream   hipStream_t
  * Allocates nothing, except the TETRA_KAHAN buffer described above.
  */
@@ -107,6 +112,8 @@ tetra_status tetra_dos_forward(const tetra_desc* d, const float* eps, const void
  *   grad_eps  device, float [nb][nk]       dL/deps, overwritten; may be NULL
  *   grad_w    device, float [nb][norb][nk] dL/dw (always FP32, of the dequantised weights),
  *                                           overwritten; may be NULL
+ *   flags     TETRA_TILE(shape) or 0; TETRA_KAHAN is accepted and ignored (each output element sums at
+ *             most eight partial values); TETRA_DETERMINISTIC gives TETRA_ERR_UNSUPPORTED
  * At least one of grad_eps, grad_w must be non-NULL. Where an energy E_j equals a corner energy the
  * loss is not differentiable; the one-sided value of the case containing E_j is returned.
  * Allocates nothing.
@@ -140,7 +147,8 @@ size_t tetra_dos_batched_workspace(const tetra_item* items, int n, int wtype, un
  * and not used by anything else until the work on `stream` completes. Each item's dos is
  * overwritten. Every item uses weight type wtype (with its own w_scale for TETRA_W_F16).
  * Allocates nothing and copies nothing to the device, so a call can be captured in a HIP graph.
- * flags must be 0 (TETRA_KAHAN is not supported here: TETRA_ERR_UNSUPPORTED).
+ * flags must be 0 (TETRA_KAHAN and TETRA_DETERMINISTIC are not supported here:
+ * TETRA_ERR_UNSUPPORTED).
  */
 tetra_status tetra_dos_batched(const tetra_item* items, int n, int wtype, unsigned flags,
                                void* workspace, size_t ws_bytes, void* stream);

@@ -37,6 +37,7 @@ TETRA_OK = 0
 TETRA_W_F32 = 0
 TETRA_W_F16 = 1
 TETRA_KAHAN = 1
+TETRA_DETERMINISTIC = 2
 MAX_NORB = 16
 # tile shapes (cubes along grid axes 1, 2, 3) selectable through the flags' bits 8..11
 TILE_SHAPES = ((4, 4, 16), (8, 8, 4), (4, 8, 8), (8, 4, 8), (4, 16, 4), (16, 4, 4))
@@ -171,12 +172,13 @@ def _shapes(eps, w, grid):
     return nk, nb, norb
 
 
-def dos_forward(eps, w, grid, e0, de, ne, *, w_scale=None, kahan=False, out=None, tile=None):
+def dos_forward(eps, w, grid, e0, de, ne, *, w_scale=None, kahan=False, deterministic=False, out=None, tile=None):
     """Orbital-resolved DOS ``[ne, norb]`` (FP32) on the current HIP stream.
 
     eps: float32 ``[nb, nk]``; w: float32 or float16 ``[nb, norb, nk]`` (float16 needs ``w_scale``
     float32 ``[nb]``); grid: (n1, n2, n3) with nk = n1*n2*n3; E_j = e0 + j*de. ``kahan`` selects the
-    exact cross-workgroup accumulation; ``tile`` an index into ``TILE_SHAPES`` (default 0).
+    exact cross-workgroup accumulation, ``deterministic`` asks for a bitwise reproducible result (the
+    same exact path); ``tile`` an index into ``TILE_SHAPES`` (default 0).
     """
     torch = _torch()
     nk, nb, norb = _shapes(eps, w, grid)
@@ -197,7 +199,8 @@ def dos_forward(eps, w, grid, e0, de, ne, *, w_scale=None, kahan=False, out=None
     st = lib().tetra_dos_forward(
         ctypes.byref(d), eps.data_ptr(), w.data_ptr(), wtype,
         w_scale.data_ptr() if w_scale is not None else None, out.data_ptr(),
-        (TETRA_KAHAN if kahan else 0) | _tile_flag(tile), _stream_handle(dev))
+        (TETRA_KAHAN if kahan else 0) | (TETRA_DETERMINISTIC if deterministic else 0) | _tile_flag(tile),
+        _stream_handle(dev))
     _check("tetra_dos_forward", st)
     return out
 

@@ -82,12 +82,14 @@ tetra_status tetra_dos_forward(const tetra_desc* d, const float* eps, const void
   if (st != TETRA_OK) return st;
   if (!eps || !w || !dos) return TETRA_ERR_ARG;
   if ((st = check_weights(wtype, w_scale)) != TETRA_OK) return st;
-  if (flags & ~(unsigned)(TETRA_KAHAN | TETRA_TILE_MASK)) return TETRA_ERR_ARG;
+  if (flags & ~(unsigned)(TETRA_KAHAN | TETRA_DETERMINISTIC | TETRA_TILE_MASK)) return TETRA_ERR_ARG;
   const int shape = (int)((flags & TETRA_TILE_MASK) >> 8);
   if (shape >= tetra::kTileShapes) return TETRA_ERR_ARG;
-  if ((flags & TETRA_KAHAN) && shape != 0) return TETRA_ERR_UNSUPPORTED;
+  // the exact accumulation is also the deterministic one
+  const bool exact = (flags & (TETRA_KAHAN | TETRA_DETERMINISTIC)) != 0;
+  if (exact && shape != 0) return TETRA_ERR_UNSUPPORTED;
   void* scratch = nullptr;
-  if (flags & TETRA_KAHAN) {
+  if (exact) {
     const hipError_t e = exact_scratch(tetra::forward_exact_scratch_bytes(*d), &scratch);
     if (e != hipSuccess) return hip_status(e);
   }
@@ -102,9 +104,10 @@ tetra_status tetra_dos_backward(const tetra_desc* d, const float* eps, const voi
   if (st != TETRA_OK) return st;
   if (!eps || !w || !grad_dos || (!grad_eps && !grad_w)) return TETRA_ERR_ARG;
   if ((st = check_weights(wtype, w_scale)) != TETRA_OK) return st;
-  if (flags & ~(unsigned)(TETRA_KAHAN | TETRA_TILE_MASK)) return TETRA_ERR_ARG;
+  if (flags & ~(unsigned)(TETRA_KAHAN | TETRA_DETERMINISTIC | TETRA_TILE_MASK)) return TETRA_ERR_ARG;
   const int shape = (int)((flags & TETRA_TILE_MASK) >> 8);
   if (shape >= tetra::kTileShapes) return TETRA_ERR_ARG;
+  if (flags & TETRA_DETERMINISTIC) return TETRA_ERR_UNSUPPORTED;
   return hip_status(tetra::backward(*d, eps, w, wtype == TETRA_W_F16 ? w_scale : nullptr, grad_dos, grad_eps,
                                     grad_w, shape, (hipStream_t)stream));
 }
@@ -120,7 +123,7 @@ tetra_status tetra_dos_batched(const tetra_item* items, int n, int wtype, unsign
                                size_t ws_bytes, void* stream) {
   if (!items || n < 1) return TETRA_ERR_ARG;
   if (wtype != TETRA_W_F32 && wtype != TETRA_W_F16) return TETRA_ERR_ARG;
-  if (flags & ~(unsigned)TETRA_KAHAN) return TETRA_ERR_ARG;
+  if (flags & ~(unsigned)(TETRA_KAHAN | TETRA_DETERMINISTIC)) return TETRA_ERR_ARG;
   for (int i = 0; i < n; ++i) {
     const tetra_item& it = items[i];
     const tetra_status st = check_desc(&it.d);
@@ -129,7 +132,7 @@ tetra_status tetra_dos_batched(const tetra_item* items, int n, int wtype, unsign
     if (check_weights(wtype, it.w_scale) != TETRA_OK) return TETRA_ERR_ARG;
     if (it.tile < 0 || it.tile >= tetra::kTileShapes) return TETRA_ERR_ARG;
   }
-  if (flags & TETRA_KAHAN) return TETRA_ERR_UNSUPPORTED;
+  if (flags & (TETRA_KAHAN | TETRA_DETERMINISTIC)) return TETRA_ERR_UNSUPPORTED;
   if (!workspace || ws_bytes < 256 * tetra::batched_launches(items, n)) return TETRA_ERR_WORKSPACE;
   std::vector<int> shapes(n);
   for (int i = 0; i < n; ++i) shapes[i] = items[i].tile;

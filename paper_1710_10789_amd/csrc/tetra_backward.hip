@@ -132,21 +132,22 @@ __global__ __launch_bounds__(NT) void dos_backward_kernel(BwdArgs a) {
       for (int t = 0; t < 6; ++t) {
         const uint32_t slots = tet_slots(t);
         float e[4];
-        int s[4];
+        int pt[4];  // LDS point of each corner, carried through the sort
+        bool sw[5] = {false, false, false, false, false};
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
-          s[l] = (slots >> (4 * l)) & 7;
-          e[l] = s_eps[pbase + point_offset(s[l])];
+          pt[l] = pbase + point_offset((slots >> (4 * l)) & 7);
+          e[l] = s_eps[pt[l]];
         }
         float gb[4][NORB];
-        float ge[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        float ge[4][1] = {{0.0f}, {0.0f}, {0.0f}, {0.0f}};
 #pragma unroll
         for (int l = 0; l < 4; ++l)
 #pragma unroll
           for (int m = 0; m < NORB; ++m) gb[l][m] = 0.0f;
         bool any = false;  // this lane has something to add for tetrahedron t
         if (active && finite4(e[0], e[1], e[2], e[3])) {
-          sort4(e, s);
+          sort4(e, pt, sw);
           int jlo, jhi;
           energy_window(e[0], e[3], a.e0, a.inv_de, c0, c1, jlo, jhi);
           if (jlo <= jhi + 2) {
@@ -157,9 +158,8 @@ __global__ __launch_bounds__(NT) void dos_backward_kernel(BwdArgs a) {
               float bb[4][NORB];
 #pragma unroll
               for (int l = 0; l < 4; ++l) {
-                const int p = pbase + point_offset(s[l]);
 #pragma unroll
-                for (int m = 0; m < NORB; ++m) bb[l][m] = s_w[p * NORB + m];
+                for (int m = 0; m < NORB; ++m) bb[l][m] = s_w[pt[l] * NORB + m];
               }
               // Per-case sub-loops (see the forward kernel): no divergence between energy cases.
               int jA, jB;
@@ -176,52 +176,71 @@ __global__ __launch_bounds__(NT) void dos_backward_kernel(BwdArgs a) {
                   sl[l] = acc;
                 }
               };
-              auto accumulate = [&](const float Gm[NORB], const float g[4], const float Eb[4]) {
+              auto accumulate = [&](const float Gm[NORB], const float g[4]) {
 #pragma unroll
-                for (int l = 0; l < 4; ++l) {
-                  ge[l] += Eb[l];
+                for (int l = 0; l < 4; ++l)
 #pragma unroll
                   for (int m = 0; m < NORB; ++m) gb[l][m] += Gm[m] * g[l];
-                }
               };
-              for (int j = jlo; j <= jA; ++j) {
-                float Gm[NORB], sl[4], g[4], Eb[4];
-                load(j, Gm, sl);
-                corner_dos_adjoint_A(cs, a.V, local_x(cs, j, a.de), sl, g, Eb);
-                accumulate(Gm, g, Eb);
+              auto add_eb = [&](const float Eb[4]) {
+#pragma unroll
+                for (int l = 0; l < 4; ++l) ge[l][0] += Eb[l];
+              };
+              if (jA >= jlo) {
+                AdjA acc;
+                adj_zero(acc);
+                for (int j = jlo; j <= jA; ++j) {
+                  float Gm[NORB], sl[4], g[4];
+                  load(j, Gm, sl);
+                  corner_dos_adjoint_acc_A(cs, local_x(cs, j, a.de), sl, g, acc);
+                  accumulate(Gm, g);
+                }
+                float Eb[4];
+                corner_dos_adjoint_finish_A(cs, a.V, acc, Eb);
+                add_eb(Eb);
               }
-              for (int j = jA + 1; j <= jB; ++j) {
-                float Gm[NORB], sl[4], g[4], Eb[4];
-                load(j, Gm, sl);
-                corner_dos_adjoint_B(cs, a.V, local_x(cs, j, a.de), sl, g, Eb);
-                accumulate(Gm, g, Eb);
+              if (jB > jA) {
+                AdjB acc;
+                adj_zero(acc);
+                for (int j = jA + 1; j <= jB; ++j) {
+                  float Gm[NORB], sl[4], g[4];
+                  load(j, Gm, sl);
+                  corner_dos_adjoint_acc_B(cs, local_x(cs, j, a.de), sl, g, acc);
+                  accumulate(Gm, g);
+                }
+                float Eb[4];
+                corner_dos_adjoint_finish_B(cs, a.V, acc, Eb);
+                add_eb(Eb);
               }
-              for (int j = jB + 1; j <= jhi; ++j) {
-                float Gm[NORB], sl[4], g[4], Eb[4];
-                load(j, Gm, sl);
-                corner_dos_adjoint_C(cs, a.V, local_x(cs, j, a.de), sl, g, Eb);
-                accumulate(Gm, g, Eb);
+              if (jhi > jB) {
+                AdjA acc;
+                adj_zero(acc);
+                for (int j = jB + 1; j <= jhi; ++j) {
+                  float Gm[NORB], sl[4], g[4];
+                  load(j, Gm, sl);
+                  corner_dos_adjoint_acc_C(cs, local_x(cs, j, a.de), sl, g, acc);
+                  accumulate(Gm, g);
+                }
+                float Eb[4];
+                corner_dos_adjoint_finish_C(cs, a.V, acc, Eb);
+                add_eb(Eb);
               }
             }
           }
         }
-        // Four rounds, one per static corner of tetrahedron t: for a fixed corner slot the target
-        // points of different lanes are distinct, so plain read-modify-writes do not race.
+        // Back to the corner order of Table I, then four rounds, one per corner of tetrahedron t: for a
+        // fixed corner slot the target points of different lanes are distinct, so plain
+        // read-modify-writes do not race.
+        unsort_rows(sw, ge);
+        unsort_rows(sw, gb);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int slot = (slots >> (4 * q)) & 7;
-          // sorted position of this corner
-          const int i = (s[0] == slot) ? 0 : (s[1] == slot) ? 1 : (s[2] == slot) ? 2 : 3;
           __syncthreads();
           if (any) {
-            float* dst = &s_pt[(pbase + point_offset(slot)) * (NORB + 1)];
-            float v = (i == 0) ? ge[0] : (i == 1) ? ge[1] : (i == 2) ? ge[2] : ge[3];
-            dst[0] += v;
+            float* dst = &s_pt[(pbase + point_offset((slots >> (4 * q)) & 7)) * (NORB + 1)];
+            dst[0] += ge[q][0];
 #pragma unroll
-            for (int m = 0; m < NORB; ++m) {
-              v = (i == 0) ? gb[0][m] : (i == 1) ? gb[1][m] : (i == 2) ? gb[2][m] : gb[3][m];
-              dst[1 + m] += v;
-            }
+            for (int m = 0; m < NORB; ++m) dst[1 + m] += gb[q][m];
           }
         }
       }

@@ -41,28 +41,51 @@ __host__ __device__ __forceinline__ bool finite4(float a, float b, float c, floa
   return __builtin_isfinite(a) && __builtin_isfinite(b) && __builtin_isfinite(c) && __builtin_isfinite(d);
 }
 
-// Compare-exchange carrying an integer tag (corner slot) with the energy.
-__host__ __device__ __forceinline__ void cswap(float& ea, int& sa, float& eb, int& sb) {
+// Compare-exchange carrying an integer tag (here the corner's LDS point index) with the energy;
+// returns whether the pair was swapped.
+__host__ __device__ __forceinline__ bool cswap(float& ea, int& pa, float& eb, int& pb) {
   const bool sw = eb < ea;
   const float lo = sw ? eb : ea;
   const float hi = sw ? ea : eb;
-  const int slo = sw ? sb : sa;
-  const int shi = sw ? sa : sb;
+  const int plo = sw ? pb : pa;
+  const int phi = sw ? pa : pb;
   ea = lo;
   eb = hi;
-  sa = slo;
-  sb = shi;
+  pa = plo;
+  pb = phi;
+  return sw;
 }
 
-// Five-comparator network: ascending energies e[0..3] with their slots. Equal energies may end in
+// Five-comparator network: ascending energies e[0..3] with their tags. Equal energies may end in
 // either order; the weights of corners with equal energies are equal, so the result does not depend
-// on it.
-__host__ __device__ __forceinline__ void sort4(float e[4], int s[4]) {
-  cswap(e[0], s[0], e[1], s[1]);
-  cswap(e[2], s[2], e[3], s[3]);
-  cswap(e[0], s[0], e[2], s[2]);
-  cswap(e[1], s[1], e[3], s[3]);
-  cswap(e[1], s[1], e[2], s[2]);
+// on it. sw[] records the exchanges, so that unsort_rows can map per-corner results back.
+__host__ __device__ __forceinline__ void sort4(float e[4], int p[4], bool sw[5]) {
+  sw[0] = cswap(e[0], p[0], e[1], p[1]);
+  sw[1] = cswap(e[2], p[2], e[3], p[3]);
+  sw[2] = cswap(e[0], p[0], e[2], p[2]);
+  sw[3] = cswap(e[1], p[1], e[3], p[3]);
+  sw[4] = cswap(e[1], p[1], e[2], p[2]);
+}
+
+__host__ __device__ __forceinline__ void sort4(float e[4], int p[4]) {
+  bool sw[5];
+  sort4(e, p, sw);
+}
+
+// Inverse of the permutation sort4 applied: rows r[0..3] (K values each, in sorted-corner order) are
+// put back into the order of the corners before the sort, by the recorded exchanges in reverse.
+template <int K>
+__host__ __device__ __forceinline__ void unsort_rows(const bool sw[5], float (&r)[4][K]) {
+  constexpr int A[5] = {0, 2, 0, 1, 1}, B[5] = {1, 3, 2, 3, 2};
+#pragma unroll
+  for (int k = 4; k >= 0; --k) {
+#pragma unroll
+    for (int v = 0; v < K; ++v) {
+      const float a = r[A[k]][v], b = r[B[k]][v];
+      r[A[k]][v] = sw[k] ? b : a;
+      r[B[k]][v] = sw[k] ? a : b;
+    }
+  }
 }
 
 // 1/x by the hardware reciprocal (within 1 ulp; +inf for +0) on the device, a division on the host.
@@ -161,39 +184,101 @@ __host__ __device__ __forceinline__ void corner_dos(const TetSetup& c, float x, 
   else corner_dos_C(c, x, g);
 }
 
-// Corner weights g[4] (as corner_dos) and, for given multipliers s[4], the gradient
-// Eb[i] = d(sum_l s_l g_l)/dE_i with respect to the four sorted corner energies at fixed E, by reverse
-// accumulation through the same expressions as corner_dos.
-// Corner weights g[4] (as corner_dos_*) and, for given multipliers s[4], the gradient
-// Eb[i] = d(sum_l s_l g_l)/dE_i with respect to the four sorted corner energies at fixed E, by reverse
-// accumulation through the same expressions; one function per energy case.
-__host__ __device__ __forceinline__ void corner_dos_adjoint_A(const TetSetup& c, float V, float x, const float s[4], float g[4], float Eb[4]) {
+// Adjoint of the corner weights for the gradient with respect to the corner energies. For multipliers
+// s[4] (one per sorted corner) the quantity sum_l s_l g_l(E) depends on the sorted energies E_1..E_4
+// through the local variables (x = E - E1, ...) and through the per-tetrahedron constants (reciprocal
+// differences and the K factors). Reverse accumulation per energy gives adjoints that are linear in s,
+// so over the energies of one case range they are summed first (the *_acc functions, which also
+// return g for the weight gradient) and pushed through the constants once (the *_finish functions),
+// which yields Eb[i] = sum over the range of d(sum_l s_l g_l)/dE_i at fixed E.
+
+struct AdjA {  // first and third case: adjoint sums of the local variable, the reciprocals, K
+  float vb, ra, rb, rc, kb;
+};
+
+__host__ __device__ __forceinline__ void adj_zero(AdjA& a) { a.vb = a.ra = a.rb = a.rc = a.kb = 0.0f; }
+
+// First case: g1 = 4K x^2 (3 - x S), g_l = 4K x^3 r_l1 (l = 2, 3, 4), S = r21 + r31 + r41.
+__host__ __device__ __forceinline__ void corner_dos_adjoint_acc_A(const TetSetup& c, float x, const float s[4], float g[4],
+                                                                  AdjA& a) {
   const float t = 4.0f * c.kA * x * x;
   const float u = t * x;
-  g[0] = t * (3.0f - x * c.sA);
+  const float w = 3.0f - x * c.sA;
+  g[0] = t * w;
   g[1] = u * c.r21;
   g[2] = u * c.r31;
   g[3] = u * c.r41;
-  float t_b = s[0] * (3.0f - x * c.sA);
-  float x_b = -s[0] * t * c.sA;
-  const float sA_b = -s[0] * t * x;
+  const float s0t = s[0] * t;
+  const float sA_b = -s0t * x;
   const float u_b = s[1] * c.r21 + s[2] * c.r31 + s[3] * c.r41;
-  float r21_b = s[1] * u, r31_b = s[2] * u, r41_b = s[3] * u;
-  t_b += u_b * x;
-  x_b += u_b * t;
-  const float kA_b = t_b * 4.0f * x * x;
-  x_b += t_b * 8.0f * c.kA * x;
-  r21_b += sA_b + kA_b * V * c.r31 * c.r41;
-  r31_b += sA_b + kA_b * V * c.r21 * c.r41;
-  r41_b += sA_b + kA_b * V * c.r21 * c.r31;
+  a.ra += s[1] * u + sA_b;
+  a.rb += s[2] * u + sA_b;
+  a.rc += s[3] * u + sA_b;
+  const float t_b = s[0] * w + u_b * x;
+  a.kb += t_b * x * x;  // dt/dK = 4 x^2: the 4 is applied in the finish
+  a.vb += u_b * t - s0t * c.sA + t_b * 8.0f * c.kA * x;
+}
+
+__host__ __device__ __forceinline__ void corner_dos_adjoint_finish_A(const TetSetup& c, float V, const AdjA& a, float Eb[4]) {
+  const float kA_b = 4.0f * a.kb * V;  // K = V r21 r31 r41
+  const float r21_b = a.ra + kA_b * c.r31 * c.r41;
+  const float r31_b = a.rb + kA_b * c.r21 * c.r41;
+  const float r41_b = a.rc + kA_b * c.r21 * c.r31;
   const float e21_b = -r21_b * c.r21 * c.r21, e31_b = -r31_b * c.r31 * c.r31, e41_b = -r41_b * c.r41 * c.r41;
-  Eb[0] = -(e21_b + e31_b + e41_b + x_b);
+  Eb[0] = -(e21_b + e31_b + e41_b + a.vb);
   Eb[1] = e21_b;
   Eb[2] = e31_b;
   Eb[3] = e41_b;
 }
 
-__host__ __device__ __forceinline__ void corner_dos_adjoint_B(const TetSetup& c, float V, float x, const float s[4], float g[4], float Eb[4]) {
+// Third case (mirror of the first with y = E4 - E): g_l = 4K' y^3 r_4l (l = 1, 2, 3),
+// g4 = 4K' y^2 (3 - y S'), S' = r41 + r42 + r43.
+__host__ __device__ __forceinline__ void corner_dos_adjoint_acc_C(const TetSetup& c, float x, const float s[4], float g[4],
+                                                                  AdjA& a) {
+  const float y = c.e41 - x;
+  const float t = 4.0f * c.kC * y * y;
+  const float u = t * y;
+  const float w = 3.0f - y * c.sC;
+  g[0] = u * c.r41;
+  g[1] = u * c.r42;
+  g[2] = u * c.r43;
+  g[3] = t * w;
+  const float s3t = s[3] * t;
+  const float sC_b = -s3t * y;
+  const float u_b = s[0] * c.r41 + s[1] * c.r42 + s[2] * c.r43;
+  a.ra += s[0] * u + sC_b;
+  a.rb += s[1] * u + sC_b;
+  a.rc += s[2] * u + sC_b;
+  const float t_b = s[3] * w + u_b * y;
+  a.kb += t_b * y * y;
+  a.vb += u_b * t - s3t * c.sC + t_b * 8.0f * c.kC * y;
+}
+
+__host__ __device__ __forceinline__ void corner_dos_adjoint_finish_C(const TetSetup& c, float V, const AdjA& a, float Eb[4]) {
+  const float kC_b = 4.0f * a.kb * V;  // K' = V r41 r42 r43
+  const float r41_b = a.ra + kC_b * c.r42 * c.r43;
+  const float r42_b = a.rb + kC_b * c.r41 * c.r43;
+  const float r43_b = a.rc + kC_b * c.r41 * c.r42;
+  const float e41_b = -r41_b * c.r41 * c.r41, e42_b = -r42_b * c.r42 * c.r42, e43_b = -r43_b * c.r43 * c.r43;
+  // y = E4 - E depends on E4 only
+  Eb[0] = -e41_b;
+  Eb[1] = -e42_b;
+  Eb[2] = -e43_b;
+  Eb[3] = e41_b + e42_b + e43_b + a.vb;
+}
+
+struct AdjB {  // middle case: adjoint sums of x, z, q, p, the reciprocals and k1, k2, k3
+  float xb, zb, qb, pb, r31b, r41b, r32b, r42b, k1b, k2b, k3b;
+};
+
+__host__ __device__ __forceinline__ void adj_zero(AdjB& a) {
+  a.xb = a.zb = a.qb = a.pb = a.r31b = a.r41b = a.r32b = a.r42b = a.k1b = a.k2b = a.k3b = 0.0f;
+}
+
+// Middle case: the printed C1, C2, C3 and their energy derivatives (with the corrected last term of
+// dw3/dE), differentiated in reverse through the same expressions as corner_dos_B.
+__host__ __device__ __forceinline__ void corner_dos_adjoint_acc_B(const TetSetup& c, float x, const float s[4], float g[4],
+                                                                  AdjB& a) {
   const float z = x - c.e21, q = c.e31 - x, p = c.e41 - x;
   const float C1 = c.k1 * x * x, dC1 = 2.0f * c.k1 * x;
   const float C2 = c.k2 * x * z * q, dC2 = c.k2 * (x * q + z * q - x * z);
@@ -218,10 +303,10 @@ __host__ __device__ __forceinline__ void corner_dos_adjoint_B(const TetSetup& c,
   float p_b = s[0] * D123 * c.r41 + s[1] * dC3 * c.r42;
   float x_b = s[2] * D12 * c.r31 + s[3] * D123 * c.r41;
   float z_b = s[2] * D23 * c.r32 + s[3] * dC3 * c.r42;
-  float r31_b = s[0] * (D12 * q - S12) + s[2] * (D12 * x + S12);
-  float r41_b = s[0] * (D123 * p - S123) + s[3] * (D123 * x + S123);
-  float r32_b = s[1] * (D23 * q - S23) + s[2] * (D23 * z + S23);
-  float r42_b = s[1] * (dC3 * p - C3) + s[3] * (dC3 * z + C3);
+  a.r31b += s[0] * (D12 * q - S12) + s[2] * (D12 * x + S12);
+  a.r41b += s[0] * (D123 * p - S123) + s[3] * (D123 * x + S123);
+  a.r32b += s[1] * (D23 * q - S23) + s[2] * (D23 * z + S23);
+  a.r42b += s[1] * (dC3 * p - C3) + s[3] * (dC3 * z + C3);
   // partial sums
   S12_b += S123_b;
   C3_b += S123_b + S23_b;
@@ -232,63 +317,37 @@ __host__ __device__ __forceinline__ void corner_dos_adjoint_B(const TetSetup& c,
   const float C1_b = S12_b;
   dC1_b += D12_b;
   // C3, dC3
-  const float k3_b = dC3_b * z * (2.0f * p - z) + C3_b * z * z * p;
+  a.k3b += dC3_b * z * (2.0f * p - z) + C3_b * z * z * p;
   z_b += dC3_b * c.k3 * (2.0f * p - 2.0f * z) + C3_b * 2.0f * c.k3 * z * p;
   p_b += dC3_b * 2.0f * c.k3 * z + C3_b * c.k3 * z * z;
   // C2, dC2
-  const float k2_b = dC2_b * (x * q + z * q - x * z) + C2_b * x * z * q;
+  a.k2b += dC2_b * (x * q + z * q - x * z) + C2_b * x * z * q;
   x_b += dC2_b * c.k2 * (q - z) + C2_b * c.k2 * z * q;
   q_b += dC2_b * c.k2 * (x + z) + C2_b * c.k2 * x * z;
   z_b += dC2_b * c.k2 * (q - x) + C2_b * c.k2 * x * q;
   // C1, dC1
-  float k1_b = dC1_b * 2.0f * x + C1_b * x * x;
+  a.k1b += dC1_b * 2.0f * x + C1_b * x * x;
   x_b += dC1_b * 2.0f * c.k1 + C1_b * 2.0f * c.k1 * x;
+  a.xb += x_b;
+  a.zb += z_b;
+  a.qb += q_b;
+  a.pb += p_b;
+}
+
+__host__ __device__ __forceinline__ void corner_dos_adjoint_finish_B(const TetSetup& c, float V, const AdjB& a, float Eb[4]) {
   // k1 = V r31 r41, k2 = k1 r32, k3 = V r32 r41 r42
-  k1_b += k2_b * c.r32;
-  r32_b += k2_b * c.k1 + k3_b * V * c.r41 * c.r42;
-  r41_b += k3_b * V * c.r32 * c.r42 + k1_b * V * c.r31;
-  const float r42_bb = r42_b + k3_b * V * c.r32 * c.r41;
-  r31_b += k1_b * V * c.r41;
+  const float k1_b = a.k1b + a.k2b * c.r32;
+  const float r32_b = a.r32b + a.k2b * c.k1 + a.k3b * V * c.r41 * c.r42;
+  const float r41_b = a.r41b + a.k3b * V * c.r32 * c.r42 + k1_b * V * c.r31;
+  const float r42_b = a.r42b + a.k3b * V * c.r32 * c.r41;
+  const float r31_b = a.r31b + k1_b * V * c.r41;
   const float e31_b = -r31_b * c.r31 * c.r31, e41_b = -r41_b * c.r41 * c.r41;
-  const float e32_b = -r32_b * c.r32 * c.r32, e42_b = -r42_bb * c.r42 * c.r42;
+  const float e32_b = -r32_b * c.r32 * c.r32, e42_b = -r42_b * c.r42 * c.r42;
   // x = E - E1, z = E - E2, q = E3 - E, p = E4 - E
-  Eb[0] = -x_b - e31_b - e41_b;
-  Eb[1] = -z_b - e32_b - e42_b;
-  Eb[2] = q_b + e31_b + e32_b;
-  Eb[3] = p_b + e41_b + e42_b;
-}
-
-__host__ __device__ __forceinline__ void corner_dos_adjoint_C(const TetSetup& c, float V, float x, const float s[4], float g[4], float Eb[4]) {
-  const float y = c.e41 - x;
-  const float t = 4.0f * c.kC * y * y;
-  const float u = t * y;
-  g[0] = u * c.r41;
-  g[1] = u * c.r42;
-  g[2] = u * c.r43;
-  g[3] = t * (3.0f - y * c.sC);
-  float t_b = s[3] * (3.0f - y * c.sC);
-  float y_b = -s[3] * t * c.sC;
-  const float sC_b = -s[3] * t * y;
-  const float u_b = s[0] * c.r41 + s[1] * c.r42 + s[2] * c.r43;
-  float r41_b = s[0] * u, r42_b = s[1] * u, r43_b = s[2] * u;
-  t_b += u_b * y;
-  y_b += u_b * t;
-  const float kC_b = t_b * 4.0f * y * y;
-  y_b += t_b * 8.0f * c.kC * y;
-  r41_b += sC_b + kC_b * V * c.r42 * c.r43;
-  r42_b += sC_b + kC_b * V * c.r41 * c.r43;
-  r43_b += sC_b + kC_b * V * c.r41 * c.r42;
-  const float e41_b = -r41_b * c.r41 * c.r41, e42_b = -r42_b * c.r42 * c.r42, e43_b = -r43_b * c.r43 * c.r43;
-  Eb[0] = -e41_b;
-  Eb[1] = -e42_b;
-  Eb[2] = -e43_b;
-  Eb[3] = e41_b + e42_b + e43_b + y_b;
-}
-
-__host__ __device__ __forceinline__ void corner_dos_adjoint(const TetSetup& c, float V, float x, const float s[4], float g[4], float Eb[4]) {
-  if (x <= c.e21) corner_dos_adjoint_A(c, V, x, s, g, Eb);
-  else if (x <= c.e31) corner_dos_adjoint_B(c, V, x, s, g, Eb);
-  else corner_dos_adjoint_C(c, V, x, s, g, Eb);
+  Eb[0] = -a.xb - e31_b - e41_b;
+  Eb[1] = -a.zb - e32_b - e42_b;
+  Eb[2] = a.qb + e31_b + e32_b;
+  Eb[3] = a.pb + e41_b + e42_b;
 }
 
 // Estimate of the window of grid indices j with E1 < E_j < E4, clipped to [lo, hi] (empty when

@@ -223,14 +223,14 @@ __device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
       for (int t = 0; t < 6; ++t) {
         const uint32_t slots = tet_slots(t);
         float e[4];
-        int s[4];
+        int pt[4];  // LDS point of each corner, carried through the sort
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
-          s[l] = (slots >> (4 * l)) & 7;
-          e[l] = s_eps[pbase + point_offset(s[l])];
+          pt[l] = pbase + point_offset((slots >> (4 * l)) & 7);
+          e[l] = s_eps[pt[l]];
         }
         if (!finite4(e[0], e[1], e[2], e[3])) continue;
-        sort4(e, s);
+        sort4(e, pt);
         int jlo, jhi;
         energy_window(e[0], e[3], a.e0, a.inv_de, c0, c1, jlo, jhi);
         if (jlo > jhi + 2) continue;  // empty even after moving both ends by one
@@ -240,9 +240,8 @@ __device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
         float bb[4][NORB];
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
-          const int p = pbase + point_offset(s[l]);
 #pragma unroll
-          for (int m = 0; m < NORB; ++m) bb[l][m] = s_w[p * NORB + m];
+          for (int m = 0; m < NORB; ++m) bb[l][m] = s_w[pt[l] * NORB + m];
         }
         // The window splits into the three energy cases; each sub-loop runs one case only, so lanes of
         // a wavefront do not execute the other cases' code.

@@ -93,6 +93,7 @@ def test_forward_rejects_bad_pointers_and_flags(L):
     assert _fwd(L, good(), flags=7 << 8) == -1  # no such tile shape
     assert _fwd(L, good(), flags=15 << 8) == -1
     assert _fwd(L, good(), flags=1 | (2 << 8)) == -2  # exact mode only with the default tile
+    assert _fwd(L, good(), flags=2 | (3 << 8)) == -2  # deterministic (= exact) mode likewise
 
 
 def test_backward_rejects_bad_arguments(L):
@@ -103,6 +104,7 @@ def test_backward_rejects_bad_arguments(L):
     assert _bwd(L, d) == -2
     assert _bwd(L, good(), flags=4) == -1
     assert _bwd(L, good(), flags=9 << 8) == -1
+    assert _bwd(L, good(), flags=2) == -2  # no deterministic adjoint
 
 
 def test_batched_rejects_bad_arguments(L):
@@ -115,5 +117,6 @@ def test_batched_rejects_bad_arguments(L):
     assert L.tetra_dos_batched(items, 1, 0, 0, FAKE, 4096, None) == -1
     items[0].tile = 0
     assert L.tetra_dos_batched(items, 1, 0, 1, FAKE, 4096, None) == -2  # no exact mode in batches
+    assert L.tetra_dos_batched(items, 1, 0, 2, FAKE, 4096, None) == -2
     assert L.tetra_dos_batched(items, 1, 0, 0, FAKE, 8, None) == -3  # workspace too small
     assert L.tetra_dos_batched_workspace(items, 1, 0, 0) == 256

@@ -66,6 +66,8 @@ def test_exact_fp32_and_repeat_spread(torch_dev, model):
     plain = [tetra.dos_forward(te, tw, GRID, e0, de, NE) for _ in range(3)]
     torch.cuda.synchronize()
     assert all(torch.equal(exact[0], x) for x in exact[1:])
+    det = tetra.dos_forward(te, tw, GRID, e0, de, NE, deterministic=True)
+    assert torch.equal(det, exact[0])  # TETRA_DETERMINISTIC takes the exact path
     err = _err(exact[0].cpu().numpy().astype(np.float64), ref)
     scale = float(plain[0].abs().max())
     spread = max(float((x - plain[0]).abs().max()) for x in plain[1:]) / scale
