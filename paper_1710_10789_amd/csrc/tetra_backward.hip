@@ -145,16 +145,22 @@ __global__ __launch_bounds__(NT) void dos_backward_kernel(BwdArgs a) {
         for (int l = 0; l < 4; ++l)
 #pragma unroll
           for (int m = 0; m < NORB; ++m) gb[l][m] = 0.0f;
-        bool any = false;  // this lane has something to add for tetrahedron t
-        if (active && finite4(e[0], e[1], e[2], e[3])) {
-          sort4(e, pt, sw);
-          int jlo, jhi;
-          energy_window(e[0], e[3], a.e0, a.inv_de, c0, c1, jlo, jhi);
-          if (jlo <= jhi + 2) {
-            const TetSetup cs = tet_setup(e, a.e0, a.V);
-            tet_window(cs, a.de, c0, c1, jlo, jhi);
-            if (jlo <= jhi) {
-              any = true;
+        // Straight-line set-up for every lane (a lane without work gets an empty window), so that
+        // the accumulators above have one definition and no copies on merging paths.
+        const bool fin = active && finite4(e[0], e[1], e[2], e[3]);
+        sort4(e, pt, sw);
+        int jlo, jhi;
+        energy_window(e[0], e[3], a.e0, a.inv_de, c0, c1, jlo, jhi);
+        const TetSetup cs = tet_setup(e, a.e0, a.V);
+        tet_window(cs, a.de, c0, c1, jlo, jhi);
+        if (!fin) {
+          jlo = c0;
+          jhi = c0 - 1;
+        }
+        const bool any = jlo <= jhi;  // this lane has something to add for tetrahedron t
+        {
+          {
+            {
               float bb[4][NORB];
 #pragma unroll
               for (int l = 0; l < 4; ++l) {
@@ -164,6 +170,7 @@ __global__ __launch_bounds__(NT) void dos_backward_kernel(BwdArgs a) {
               // Per-case sub-loops (see the forward kernel): no divergence between energy cases.
               int jA, jB;
               case_split(cs, a.de, a.inv_de, jlo, jhi, jA, jB);
+              if (!any) jA = jB = jhi;
               auto load = [&](int j, float Gm[NORB], float sl[4]) {
                 const float* Gj = &s_G[(j - c0) * NORB];
 #pragma unroll
