@@ -194,42 +194,49 @@ __global__ __launch_bounds__(NT) void dos_backward_kernel(BwdArgs a) {
                 for (int l = 0; l < 4; ++l) ge[l][0] += Eb[l];
               };
               if (jA >= jlo) {
-                AdjA acc;
-                adj_zero(acc);
+                float m[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
                 for (int j = jlo; j <= jA; ++j) {
                   float Gm[NORB], sl[4], g[4];
                   load(j, Gm, sl);
-                  corner_dos_adjoint_acc_A(cs, local_x(cs, j, a.de), sl, g, acc);
+                  const float x = local_x(cs, j, a.de);
+                  corner_dos_A(cs, x, g);
+                  corner_dos_moments_acc_A(x, sl, m);
                   accumulate(Gm, g);
                 }
                 float Eb[4];
-                corner_dos_adjoint_finish_A(cs, a.V, acc, Eb);
+                corner_dos_moments_finish_A(cs, a.V, m, Eb);
                 add_eb(Eb);
               }
               if (jB > jA) {
-                AdjB acc;
-                adj_zero(acc);
+                float M[4][4];
+#pragma unroll
+                for (int l = 0; l < 4; ++l)
+#pragma unroll
+                  for (int k = 0; k < 4; ++k) M[l][k] = 0.0f;
                 for (int j = jA + 1; j <= jB; ++j) {
                   float Gm[NORB], sl[4], g[4];
                   load(j, Gm, sl);
-                  corner_dos_adjoint_acc_B(cs, local_x(cs, j, a.de), sl, g, acc);
+                  const float z = local_z(cs, j, a.de);
+                  corner_dos_B(cs, z, g);
+                  corner_dos_moments_acc_B(z, sl, M);
                   accumulate(Gm, g);
                 }
                 float Eb[4];
-                corner_dos_adjoint_finish_B(cs, a.V, acc, Eb);
+                corner_dos_moments_finish_B(cs, a.V, M, Eb);
                 add_eb(Eb);
               }
               if (jhi > jB) {
-                AdjA acc;
-                adj_zero(acc);
+                float m[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
                 for (int j = jB + 1; j <= jhi; ++j) {
                   float Gm[NORB], sl[4], g[4];
                   load(j, Gm, sl);
-                  corner_dos_adjoint_acc_C(cs, local_x(cs, j, a.de), sl, g, acc);
+                  const float y = local_y(cs, j, a.de);
+                  corner_dos_C(cs, y, g);
+                  corner_dos_moments_acc_C(y, sl, m);
                   accumulate(Gm, g);
                 }
                 float Eb[4];
-                corner_dos_adjoint_finish_C(cs, a.V, acc, Eb);
+                corner_dos_moments_finish_C(cs, a.V, m, Eb);
                 add_eb(Eb);
               }
             }

@@ -11,9 +11,10 @@
 //       q = E3 - E, p = E4 - E, and the last term of dw3/dE taken as (C2 + C3)/E32, the form
 //       that is the energy derivative of the printed w3.
 //
-// with V = V_T / (4 V_G). Energies are handled in a local frame: x = E_j - E1 is formed once per
-// (tetrahedron, band, j) from e0 - E1 split into a head and an exact tail, so that the absolute
-// magnitude of the energies does not cost resolution.
+// with V = V_T / (4 V_G). Energies are handled in local frames: x = E_j - E1 (z = E_j - E2 in the
+// middle case, y = E4 - E_j in the third) is formed per (tetrahedron, band, j) from e0 - E1 (e0 - E2,
+// e0 - E4) split into a head and an exact tail, so that the absolute magnitude of the energies does
+// not cost resolution.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -107,7 +108,10 @@ __host__ __device__ __forceinline__ void two_sum(float a, float b, float& hi, fl
 // Per (tetrahedron, band) constants of the corner-weight evaluation.
 struct TetSetup {
   float d_hi, d_lo;            // e0 - E1 = d_hi + d_lo exactly
+  float f_hi, f_lo;            // e0 - E4 = f_hi + f_lo exactly
+  float h_hi, h_lo;            // e0 - E2 = h_hi + h_lo exactly
   float e21, e31, e41;         // E2 - E1, E3 - E1, E4 - E1
+  float e32, e42;              // E3 - E2, E4 - E2 (each rounded once, exact when the two are close)
   float kA, sA;                // first case: K, S
   float kC, sC;                // third case: K', S'
   float r21, r31, r41, r32, r42, r43;
@@ -117,10 +121,14 @@ struct TetSetup {
 __host__ __device__ __forceinline__ TetSetup tet_setup(const float e[4], float e0, float V) {
   TetSetup c;
   two_sum(e0, -e[0], c.d_hi, c.d_lo);
+  two_sum(e0, -e[3], c.f_hi, c.f_lo);
+  two_sum(e0, -e[1], c.h_hi, c.h_lo);
   c.e21 = e[1] - e[0];
   c.e31 = e[2] - e[0];
   c.e41 = e[3] - e[0];
-  const float e32 = e[2] - e[1], e42 = e[3] - e[1], e43 = e[3] - e[2];
+  c.e32 = e[2] - e[1];
+  c.e42 = e[3] - e[1];
+  const float e32 = c.e32, e42 = c.e42, e43 = e[3] - e[2];
   // Reciprocals of zero differences are infinite; the case that would use them is never selected.
   c.r21 = rcp(c.e21);
   c.r31 = rcp(c.e31);
@@ -143,8 +151,19 @@ __host__ __device__ __forceinline__ float local_x(const TetSetup& c, int j, floa
   return __builtin_fmaf((float)j, de, c.d_hi) + c.d_lo;
 }
 
-// dw_l/dE at local energy x, sorted-corner order, one function per energy case:
-// A: 0 < x <= E21 (E1 < E <= E2), B: E21 < x <= E31 (E2 < E <= E3), C: E31 < x < E41 (E3 < E < E4).
+// z = E_j - E2 (the middle case's variable).
+__host__ __device__ __forceinline__ float local_z(const TetSetup& c, int j, float de) {
+  return __builtin_fmaf((float)j, de, c.h_hi) + c.h_lo;
+}
+
+// y = E4 - E_j, accurate near E4 (the third case's variable).
+__host__ __device__ __forceinline__ float local_y(const TetSetup& c, int j, float de) {
+  return -(__builtin_fmaf((float)j, de, c.f_hi) + c.f_lo);
+}
+
+// dw_l/dE in sorted-corner order, one function per energy case: A at x = E - E1 with 0 < x <= E21
+// (E1 < E <= E2), B at z = E - E2 with 0 < z <= E32 (E2 < E <= E3), C at y = E4 - E with 0 < y < E43
+// (E3 < E < E4).
 __host__ __device__ __forceinline__ void corner_dos_A(const TetSetup& c, float x, float g[4]) {
   const float t = 4.0f * c.kA * x * x;
   const float u = t * x;
@@ -154,8 +173,10 @@ __host__ __device__ __forceinline__ void corner_dos_A(const TetSetup& c, float x
   g[3] = u * c.r41;
 }
 
-__host__ __device__ __forceinline__ void corner_dos_B(const TetSetup& c, float x, float g[4]) {
-  const float z = x - c.e21, q = c.e31 - x, p = c.e41 - x;
+__host__ __device__ __forceinline__ void corner_dos_B(const TetSetup& c, float z, float g[4]) {
+  // x = E - E1, q = E3 - E, p = E4 - E from z = E - E2 and differences to E2: q and p are divided by
+  // E32 and E42 below, so they are formed where those differences are exact for close energies.
+  const float x = z + c.e21, q = c.e32 - z, p = c.e42 - z;
   const float C1 = c.k1 * x * x, dC1 = 2.0f * c.k1 * x;
   const float C2 = c.k2 * x * z * q, dC2 = c.k2 * (x * q + z * q - x * z);
   const float C3 = c.k3 * z * z * p, dC3 = c.k3 * z * (2.0f * p - z);
@@ -167,8 +188,7 @@ __host__ __device__ __forceinline__ void corner_dos_B(const TetSetup& c, float x
   g[3] = (D123 * x + S123) * c.r41 + (dC3 * z + C3) * c.r42;
 }
 
-__host__ __device__ __forceinline__ void corner_dos_C(const TetSetup& c, float x, float g[4]) {
-  const float y = c.e41 - x;
+__host__ __device__ __forceinline__ void corner_dos_C(const TetSetup& c, float y, float g[4]) {
   const float t = 4.0f * c.kC * y * y;
   const float u = t * y;
   g[0] = u * c.r41;
@@ -177,177 +197,179 @@ __host__ __device__ __forceinline__ void corner_dos_C(const TetSetup& c, float x
   g[3] = t * (3.0f - y * c.sC);
 }
 
-// dw_l/dE at local energy x (0 < x < E41 assumed by the caller).
-__host__ __device__ __forceinline__ void corner_dos(const TetSetup& c, float x, float g[4]) {
-  if (x <= c.e21) corner_dos_A(c, x, g);
-  else if (x <= c.e31) corner_dos_B(c, x, g);
-  else corner_dos_C(c, x, g);
+// Adjoint of the corner weights by moments. For multipliers s_l (one per sorted corner) summed over the
+// energies of one case range, F = sum_j sum_l s_l g_l(E_j) is a combination of a few moments
+// sum_j s_l t_j^k of the range's local variable t (x = E - E1 in the first case, y = E4 - E in the
+// third, z = E - E2 in the middle one), because every corner weight is a polynomial in t on its case
+// range. The per-energy work is the moments (*_acc); the derivative of F with respect to the four
+// sorted corner energies at fixed E_j is taken once per range through the per-tetrahedron constants
+// (*_finish), in reverse.
+
+// First case: g1 = 4K x^2 (3 - x S), g_l = 4K x^3 r_l1 (l = 2, 3, 4), K = V r21 r31 r41, S = r21 + r31 + r41.
+// Moments m[9]: s1 x, s1 x^2, s1 x^3, s_l x^2 (l = 2, 3, 4), s_l x^3 (l = 2, 3, 4).
+__host__ __device__ __forceinline__ void corner_dos_moments_acc_A(float x, const float s[4], float m[9]) {
+  const float x2 = x * x, x3 = x2 * x;
+  m[0] = __builtin_fmaf(s[0], x, m[0]);
+  m[1] = __builtin_fmaf(s[0], x2, m[1]);
+  m[2] = __builtin_fmaf(s[0], x3, m[2]);
+#pragma unroll
+  for (int l = 1; l < 4; ++l) {
+    m[2 + l] = __builtin_fmaf(s[l], x2, m[2 + l]);
+    m[5 + l] = __builtin_fmaf(s[l], x3, m[5 + l]);
+  }
 }
 
-// Adjoint of the corner weights for the gradient with respect to the corner energies. For multipliers
-// s[4] (one per sorted corner) the quantity sum_l s_l g_l(E) depends on the sorted energies E_1..E_4
-// through the local variables (x = E - E1, ...) and through the per-tetrahedron constants (reciprocal
-// differences and the K factors). Reverse accumulation per energy gives adjoints that are linear in s,
-// so over the energies of one case range they are summed first (the *_acc functions, which also
-// return g for the weight gradient) and pushed through the constants once (the *_finish functions),
-// which yields Eb[i] = sum over the range of d(sum_l s_l g_l)/dE_i at fixed E.
-
-struct AdjA {  // first and third case: adjoint sums of the local variable, the reciprocals, K
-  float vb, ra, rb, rc, kb;
-};
-
-__host__ __device__ __forceinline__ void adj_zero(AdjA& a) { a.vb = a.ra = a.rb = a.rc = a.kb = 0.0f; }
-
-// First case: g1 = 4K x^2 (3 - x S), g_l = 4K x^3 r_l1 (l = 2, 3, 4), S = r21 + r31 + r41.
-__host__ __device__ __forceinline__ void corner_dos_adjoint_acc_A(const TetSetup& c, float x, const float s[4], float g[4],
-                                                                  AdjA& a) {
-  const float t = 4.0f * c.kA * x * x;
-  const float u = t * x;
-  const float w = 3.0f - x * c.sA;
-  g[0] = t * w;
-  g[1] = u * c.r21;
-  g[2] = u * c.r31;
-  g[3] = u * c.r41;
-  const float s0t = s[0] * t;
-  const float sA_b = -s0t * x;
-  const float u_b = s[1] * c.r21 + s[2] * c.r31 + s[3] * c.r41;
-  a.ra += s[1] * u + sA_b;
-  a.rb += s[2] * u + sA_b;
-  a.rc += s[3] * u + sA_b;
-  const float t_b = s[0] * w + u_b * x;
-  a.kb += t_b * x * x;  // dt/dK = 4 x^2: the 4 is applied in the finish
-  a.vb += u_b * t - s0t * c.sA + t_b * 8.0f * c.kA * x;
+__host__ __device__ __forceinline__ void corner_dos_moments_finish_A(const TetSetup& c, float V, const float m[9], float Eb[4]) {
+  // F = 4K T, T = 3 sum s1 x^2 - S sum s1 x^3 + sum_l r_l1 sum s_l x^3
+  const float T = 3.0f * m[1] - c.sA * m[2] + c.r21 * m[6] + c.r31 * m[7] + c.r41 * m[8];
+  const float K4 = 4.0f * c.kA, V4T = 4.0f * V * T;
+  const float F21 = V4T * c.r31 * c.r41 + K4 * (m[6] - m[2]);
+  const float F31 = V4T * c.r21 * c.r41 + K4 * (m[7] - m[2]);
+  const float F41 = V4T * c.r21 * c.r31 + K4 * (m[8] - m[2]);
+  // dF/dx summed over the range (x = E - E1 moves with E1)
+  const float Fx = K4 * (6.0f * m[0] - 3.0f * c.sA * m[1] + 3.0f * (c.r21 * m[3] + c.r31 * m[4] + c.r41 * m[5]));
+  const float e21b = -F21 * c.r21 * c.r21, e31b = -F31 * c.r31 * c.r31, e41b = -F41 * c.r41 * c.r41;
+  Eb[0] = -(e21b + e31b + e41b) - Fx;
+  Eb[1] = e21b;
+  Eb[2] = e31b;
+  Eb[3] = e41b;
 }
 
-__host__ __device__ __forceinline__ void corner_dos_adjoint_finish_A(const TetSetup& c, float V, const AdjA& a, float Eb[4]) {
-  const float kA_b = 4.0f * a.kb * V;  // K = V r21 r31 r41
-  const float r21_b = a.ra + kA_b * c.r31 * c.r41;
-  const float r31_b = a.rb + kA_b * c.r21 * c.r41;
-  const float r41_b = a.rc + kA_b * c.r21 * c.r31;
-  const float e21_b = -r21_b * c.r21 * c.r21, e31_b = -r31_b * c.r31 * c.r31, e41_b = -r41_b * c.r41 * c.r41;
-  Eb[0] = -(e21_b + e31_b + e41_b + a.vb);
-  Eb[1] = e21_b;
-  Eb[2] = e31_b;
-  Eb[3] = e41_b;
+// Third case (mirror of the first, y = E4 - E): g_l = 4K' y^3 r_4l (l = 1, 2, 3), g4 = 4K' y^2 (3 - y S'),
+// K' = V r41 r42 r43, S' = r41 + r42 + r43. Moments m[9]: s4 y, s4 y^2, s4 y^3, s_l y^2 (l = 1, 2, 3),
+// s_l y^3 (l = 1, 2, 3).
+__host__ __device__ __forceinline__ void corner_dos_moments_acc_C(float y, const float s[4], float m[9]) {
+  const float y2 = y * y, y3 = y2 * y;
+  m[0] = __builtin_fmaf(s[3], y, m[0]);
+  m[1] = __builtin_fmaf(s[3], y2, m[1]);
+  m[2] = __builtin_fmaf(s[3], y3, m[2]);
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    m[3 + l] = __builtin_fmaf(s[l], y2, m[3 + l]);
+    m[6 + l] = __builtin_fmaf(s[l], y3, m[6 + l]);
+  }
 }
 
-// Third case (mirror of the first with y = E4 - E): g_l = 4K' y^3 r_4l (l = 1, 2, 3),
-// g4 = 4K' y^2 (3 - y S'), S' = r41 + r42 + r43.
-__host__ __device__ __forceinline__ void corner_dos_adjoint_acc_C(const TetSetup& c, float x, const float s[4], float g[4],
-                                                                  AdjA& a) {
-  const float y = c.e41 - x;
-  const float t = 4.0f * c.kC * y * y;
-  const float u = t * y;
-  const float w = 3.0f - y * c.sC;
-  g[0] = u * c.r41;
-  g[1] = u * c.r42;
-  g[2] = u * c.r43;
-  g[3] = t * w;
-  const float s3t = s[3] * t;
-  const float sC_b = -s3t * y;
-  const float u_b = s[0] * c.r41 + s[1] * c.r42 + s[2] * c.r43;
-  a.ra += s[0] * u + sC_b;
-  a.rb += s[1] * u + sC_b;
-  a.rc += s[2] * u + sC_b;
-  const float t_b = s[3] * w + u_b * y;
-  a.kb += t_b * y * y;
-  a.vb += u_b * t - s3t * c.sC + t_b * 8.0f * c.kC * y;
+__host__ __device__ __forceinline__ void corner_dos_moments_finish_C(const TetSetup& c, float V, const float m[9], float Eb[4]) {
+  const float T = 3.0f * m[1] - c.sC * m[2] + c.r41 * m[6] + c.r42 * m[7] + c.r43 * m[8];
+  const float K4 = 4.0f * c.kC, V4T = 4.0f * V * T;
+  const float F41 = V4T * c.r42 * c.r43 + K4 * (m[6] - m[2]);
+  const float F42 = V4T * c.r41 * c.r43 + K4 * (m[7] - m[2]);
+  const float F43 = V4T * c.r41 * c.r42 + K4 * (m[8] - m[2]);
+  // dF/dy summed over the range (y = E4 - E moves with E4)
+  const float Fy = K4 * (6.0f * m[0] - 3.0f * c.sC * m[1] + 3.0f * (c.r41 * m[3] + c.r42 * m[4] + c.r43 * m[5]));
+  const float e41b = -F41 * c.r41 * c.r41, e42b = -F42 * c.r42 * c.r42, e43b = -F43 * c.r43 * c.r43;
+  Eb[0] = -e41b;
+  Eb[1] = -e42b;
+  Eb[2] = -e43b;
+  Eb[3] = e41b + e42b + e43b + Fy;
 }
 
-__host__ __device__ __forceinline__ void corner_dos_adjoint_finish_C(const TetSetup& c, float V, const AdjA& a, float Eb[4]) {
-  const float kC_b = 4.0f * a.kb * V;  // K' = V r41 r42 r43
-  const float r41_b = a.ra + kC_b * c.r42 * c.r43;
-  const float r42_b = a.rb + kC_b * c.r41 * c.r43;
-  const float r43_b = a.rc + kC_b * c.r41 * c.r42;
-  const float e41_b = -r41_b * c.r41 * c.r41, e42_b = -r42_b * c.r42 * c.r42, e43_b = -r43_b * c.r43 * c.r43;
-  // y = E4 - E depends on E4 only
-  Eb[0] = -e41_b;
-  Eb[1] = -e42_b;
-  Eb[2] = -e43_b;
-  Eb[3] = e41_b + e42_b + e43_b + a.vb;
+// Middle case by moments. On (E2, E3] every corner weight is a cubic in z = E - E2,
+//   g_l(z) = sum_k c_lk z^k,
+// whose coefficients are rational functions of a = E21, b = E32, c = E42 (with k1 = V/(E31 E41)):
+//   g1: 4 a k1 (ab + ac + 2bc) / (E31 E41),  -12 k1 (a^2 - bc) / (E31 E41),  -12 k1 (2a + b + c) / (E31 E41),
+//       4 k1 (a^2 + 2ab + 2ac + b^2 + bc + c^2) / (b c E31 E41)
+//   g2: 4 a k1,  12 k1,  -12 k1 (a + b + c) / (b c),  4 k1 (ab + ac + b^2 + bc + c^2) / (b^2 c^2)
+//   g3: 4 a^2 k1 / E31,  12 a k1 / E31,  12 k1 / E31,  -4 k1 (a^2 + 2ab + ac + b^2 + 2bc) / (b^2 c E31)
+//   g4: 4 a^2 k1 / E41,  12 a k1 / E41,  12 k1 / E41,  -4 k1 (a^2 + ab + 2ac + 2bc + c^2) / (b c^2 E41)
+// (the expansion of the printed middle-case formulas, with the corrected last term of dw3/dE). Over a
+// range of energies, sum_j sum_l s_l g_l(z_j) = sum_lk c_lk M_lk with the moments M_lk = sum_j s_l z_j^k,
+// so the gradient with respect to the corner energies needs only the 16 moments per range: the
+// per-energy work is the moments, and the derivative through the coefficients is taken once, in
+// reverse, by corner_dos_moments_finish_B.
+__host__ __device__ __forceinline__ void corner_dos_moments_acc_B(float z, const float s[4], float M[4][4]) {
+  const float z2 = z * z, z3 = z2 * z;
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    M[l][0] += s[l];
+    M[l][1] = __builtin_fmaf(s[l], z, M[l][1]);
+    M[l][2] = __builtin_fmaf(s[l], z2, M[l][2]);
+    M[l][3] = __builtin_fmaf(s[l], z3, M[l][3]);
+  }
 }
 
-struct AdjB {  // middle case: adjoint sums of x, z, q, p, the reciprocals and k1, k2, k3
-  float xb, zb, qb, pb, r31b, r41b, r32b, r42b, k1b, k2b, k3b;
-};
-
-__host__ __device__ __forceinline__ void adj_zero(AdjB& a) {
-  a.xb = a.zb = a.qb = a.pb = a.r31b = a.r41b = a.r32b = a.r42b = a.k1b = a.k2b = a.k3b = 0.0f;
-}
-
-// Middle case: the printed C1, C2, C3 and their energy derivatives (with the corrected last term of
-// dw3/dE), differentiated in reverse through the same expressions as corner_dos_B.
-__host__ __device__ __forceinline__ void corner_dos_adjoint_acc_B(const TetSetup& c, float x, const float s[4], float g[4],
-                                                                  AdjB& a) {
-  const float z = x - c.e21, q = c.e31 - x, p = c.e41 - x;
-  const float C1 = c.k1 * x * x, dC1 = 2.0f * c.k1 * x;
-  const float C2 = c.k2 * x * z * q, dC2 = c.k2 * (x * q + z * q - x * z);
-  const float C3 = c.k3 * z * z * p, dC3 = c.k3 * z * (2.0f * p - z);
-  const float S12 = C1 + C2, D12 = dC1 + dC2, S23 = C2 + C3, D23 = dC2 + dC3;
-  const float S123 = S12 + C3, D123 = D12 + dC3;
-  g[0] = dC1 + (D12 * q - S12) * c.r31 + (D123 * p - S123) * c.r41;
-  g[1] = D123 + (D23 * q - S23) * c.r32 + (dC3 * p - C3) * c.r42;
-  g[2] = (D12 * x + S12) * c.r31 + (D23 * z + S23) * c.r32;
-  g[3] = (D123 * x + S123) * c.r41 + (dC3 * z + C3) * c.r42;
-  // adjoints of the quantities the four outputs read
-  float dC1_b = s[0];
-  float D12_b = (s[0] * q + s[2] * x) * c.r31;
-  float S12_b = (s[2] - s[0]) * c.r31;
-  const float D123_b = s[0] * p * c.r41 + s[1] + s[3] * x * c.r41;
-  const float S123_b = (s[3] - s[0]) * c.r41;
-  const float D23_b = (s[1] * q + s[2] * z) * c.r32;
-  const float S23_b = (s[2] - s[1]) * c.r32;
-  float dC3_b = (s[1] * p + s[3] * z) * c.r42;
-  float C3_b = (s[3] - s[1]) * c.r42;
-  float q_b = s[0] * D12 * c.r31 + s[1] * D23 * c.r32;
-  float p_b = s[0] * D123 * c.r41 + s[1] * dC3 * c.r42;
-  float x_b = s[2] * D12 * c.r31 + s[3] * D123 * c.r41;
-  float z_b = s[2] * D23 * c.r32 + s[3] * dC3 * c.r42;
-  a.r31b += s[0] * (D12 * q - S12) + s[2] * (D12 * x + S12);
-  a.r41b += s[0] * (D123 * p - S123) + s[3] * (D123 * x + S123);
-  a.r32b += s[1] * (D23 * q - S23) + s[2] * (D23 * z + S23);
-  a.r42b += s[1] * (dC3 * p - C3) + s[3] * (dC3 * z + C3);
-  // partial sums
-  S12_b += S123_b;
-  C3_b += S123_b + S23_b;
-  D12_b += D123_b;
-  dC3_b += D123_b + D23_b;
-  const float C2_b = S23_b + S12_b;
-  const float dC2_b = D23_b + D12_b;
-  const float C1_b = S12_b;
-  dC1_b += D12_b;
-  // C3, dC3
-  a.k3b += dC3_b * z * (2.0f * p - z) + C3_b * z * z * p;
-  z_b += dC3_b * c.k3 * (2.0f * p - 2.0f * z) + C3_b * 2.0f * c.k3 * z * p;
-  p_b += dC3_b * 2.0f * c.k3 * z + C3_b * c.k3 * z * z;
-  // C2, dC2
-  a.k2b += dC2_b * (x * q + z * q - x * z) + C2_b * x * z * q;
-  x_b += dC2_b * c.k2 * (q - z) + C2_b * c.k2 * z * q;
-  q_b += dC2_b * c.k2 * (x + z) + C2_b * c.k2 * x * z;
-  z_b += dC2_b * c.k2 * (q - x) + C2_b * c.k2 * x * q;
-  // C1, dC1
-  a.k1b += dC1_b * 2.0f * x + C1_b * x * x;
-  x_b += dC1_b * 2.0f * c.k1 + C1_b * 2.0f * c.k1 * x;
-  a.xb += x_b;
-  a.zb += z_b;
-  a.qb += q_b;
-  a.pb += p_b;
-}
-
-__host__ __device__ __forceinline__ void corner_dos_adjoint_finish_B(const TetSetup& c, float V, const AdjB& a, float Eb[4]) {
-  // k1 = V r31 r41, k2 = k1 r32, k3 = V r32 r41 r42
-  const float k1_b = a.k1b + a.k2b * c.r32;
-  const float r32_b = a.r32b + a.k2b * c.k1 + a.k3b * V * c.r41 * c.r42;
-  const float r41_b = a.r41b + a.k3b * V * c.r32 * c.r42 + k1_b * V * c.r31;
-  const float r42_b = a.r42b + a.k3b * V * c.r32 * c.r41;
-  const float r31_b = a.r31b + k1_b * V * c.r41;
-  const float e31_b = -r31_b * c.r31 * c.r31, e41_b = -r41_b * c.r41 * c.r41;
-  const float e32_b = -r32_b * c.r32 * c.r32, e42_b = -r42_b * c.r42 * c.r42;
-  // x = E - E1, z = E - E2, q = E3 - E, p = E4 - E
-  Eb[0] = -a.xb - e31_b - e41_b;
-  Eb[1] = -a.zb - e32_b - e42_b;
-  Eb[2] = a.qb + e31_b + e32_b;
-  Eb[3] = a.pb + e41_b + e42_b;
+__host__ __device__ __forceinline__ void corner_dos_moments_finish_B(const TetSetup& c, float V, const float M[4][4],
+                                                                     float Eb[4]) {
+  const float a = c.e21, b = c.e32, cc = c.e42;
+  const float r31 = c.r31, r41 = c.r41, rb = c.r32, rc = c.r42;
+  const float k1 = V * r31 * r41;
+  const float ab = a * b, ac = a * cc, bc = b * cc, aa = a * a, bb = b * b, ccc = cc * cc;
+  const float P1 = aa + 2.0f * ab + 2.0f * ac + bb + bc + ccc;
+  const float P2 = ab + ac + bb + bc + ccc;
+  const float P3 = aa + 2.0f * ab + ac + bb + 2.0f * bc;
+  const float P4 = aa + ab + 2.0f * ac + 2.0f * bc + ccc;
+  const float Q0 = ab + ac + 2.0f * bc;
+  const float rbc = rb * rc;
+  const float S = a + b + cc;
+  // coefficients / k1, for the derivative through z (z = E - E2 moves with E2)
+  const float u0 = 4.0f * a * Q0, u1 = -12.0f * (aa - bc), u2 = -12.0f * (2.0f * a + b + cc);
+  const float w13 = 4.0f * P1 * rbc;
+  const float w22 = -12.0f * S * rbc, w23 = 4.0f * P2 * rbc * rbc;
+  const float w33 = -4.0f * P3 * rb * rbc, w43 = -4.0f * P4 * rc * rbc;
+  // F / k1 = T = T1 + T2 + T3 + T4
+  const float X1 = u0 * M[0][0] + u1 * M[0][1] + u2 * M[0][2] + w13 * M[0][3];
+  const float T2 = 4.0f * a * M[1][0] + 12.0f * M[1][1] + w22 * M[1][2] + w23 * M[1][3];
+  const float W3 = 4.0f * aa * M[2][0] + 12.0f * a * M[2][1] + 12.0f * M[2][2];
+  const float X3 = W3 + w33 * M[2][3];
+  const float W4 = 4.0f * aa * M[3][0] + 12.0f * a * M[3][1] + 12.0f * M[3][2];
+  const float X4 = W4 + w43 * M[3][3];
+  const float T = r31 * r41 * X1 + T2 + r31 * X3 + r41 * X4;
+  // dF/dz summed over the range: sum_{l, k >= 1} k c_lk M_l,k-1
+  const float dz1 = r31 * r41 * (u1 * M[0][0] + 2.0f * u2 * M[0][1] + 3.0f * w13 * M[0][2]);
+  const float dz2 = 12.0f * M[1][0] + 2.0f * w22 * M[1][1] + 3.0f * w23 * M[1][2];
+  const float dz3 = r31 * (12.0f * a * M[2][0] + 24.0f * M[2][1] + 3.0f * w33 * M[2][2]);
+  const float dz4 = r41 * (12.0f * a * M[3][0] + 24.0f * M[3][1] + 3.0f * w43 * M[3][2]);
+  const float Fz = k1 * (dz1 + dz2 + dz3 + dz4);
+  // reverse sweep of F = k1 T with respect to a, b, c and the reciprocals
+  const float Tb = k1;
+  float r31b = V * r41 * T, r41b = V * r31 * T, rbb = 0.0f, rcb = 0.0f;
+  float ab_ = 0.0f, bb_ = 0.0f, cb_ = 0.0f;
+  // T1 = r31 r41 X1
+  r31b += r41 * X1 * Tb;
+  r41b += r31 * X1 * Tb;
+  const float X1b = r31 * r41 * Tb;
+  ab_ += X1b * (M[0][0] * (4.0f * Q0 + 4.0f * a * (b + cc)) - 24.0f * a * M[0][1] - 24.0f * M[0][2]);
+  bb_ += X1b * (4.0f * a * (a + 2.0f * cc) * M[0][0] + 12.0f * cc * M[0][1] - 12.0f * M[0][2]);
+  cb_ += X1b * (4.0f * a * (a + 2.0f * b) * M[0][0] + 12.0f * b * M[0][1] - 12.0f * M[0][2]);
+  const float P1b = 4.0f * rbc * M[0][3] * X1b;
+  rbb += 4.0f * P1 * rc * M[0][3] * X1b;
+  rcb += 4.0f * P1 * rb * M[0][3] * X1b;
+  // T2
+  ab_ += Tb * (4.0f * M[1][0] - 12.0f * rbc * M[1][2]);
+  bb_ += Tb * (-12.0f * rbc * M[1][2]);
+  cb_ += Tb * (-12.0f * rbc * M[1][2]);
+  rbb += Tb * (-12.0f * S * rc * M[1][2] + 8.0f * P2 * rb * rc * rc * M[1][3]);
+  rcb += Tb * (-12.0f * S * rb * M[1][2] + 8.0f * P2 * rb * rb * rc * M[1][3]);
+  const float P2b = 4.0f * rbc * rbc * M[1][3] * Tb;
+  // T3 = r31 X3
+  r31b += X3 * Tb;
+  const float X3b = r31 * Tb;
+  ab_ += X3b * (8.0f * a * M[2][0] + 12.0f * M[2][1]);
+  const float P3b = -4.0f * rb * rbc * M[2][3] * X3b;
+  rbb += -8.0f * P3 * rbc * M[2][3] * X3b;
+  rcb += -4.0f * P3 * rb * rb * M[2][3] * X3b;
+  // T4 = r41 X4
+  r41b += X4 * Tb;
+  const float X4b = r41 * Tb;
+  ab_ += X4b * (8.0f * a * M[3][0] + 12.0f * M[3][1]);
+  const float P4b = -4.0f * rc * rbc * M[3][3] * X4b;
+  rbb += -4.0f * P4 * rc * rc * M[3][3] * X4b;
+  rcb += -8.0f * P4 * rbc * M[3][3] * X4b;
+  // the polynomials P1..P4
+  ab_ += P1b * (2.0f * S) + P2b * (b + cc) + P3b * (2.0f * a + 2.0f * b + cc) + P4b * (2.0f * a + b + 2.0f * cc);
+  bb_ += P1b * (2.0f * a + 2.0f * b + cc) + P2b * (a + 2.0f * b + cc) + P3b * (2.0f * S) + P4b * (a + 2.0f * cc);
+  cb_ += P1b * (2.0f * a + b + 2.0f * cc) + P2b * (a + b + 2.0f * cc) + P3b * (a + 2.0f * b) + P4b * (2.0f * S);
+  // reciprocals: r31 = 1/(a + b), r41 = 1/(a + c), rb = 1/b, rc = 1/c
+  const float d31 = -r31b * r31 * r31, d41 = -r41b * r41 * r41;
+  ab_ += d31 + d41;
+  bb_ += d31 - rbb * rb * rb;
+  cb_ += d41 - rcb * rc * rc;
+  // a = E2 - E1, b = E3 - E2, c = E4 - E2, z = E - E2
+  Eb[0] = -ab_;
+  Eb[1] = ab_ - bb_ - cb_ - Fz;
+  Eb[2] = bb_;
+  Eb[3] = cb_;
 }
 
 // Estimate of the window of grid indices j with E1 < E_j < E4, clipped to [lo, hi] (empty when

@@ -29,6 +29,8 @@
 // Workgroups are assigned so that each XCD (eight per MI355X, each with its own L2) works through a
 // contiguous range of tiles of the same band, keeping shared halo points in one L2.
 
+#include <atomic>
+
 #include "tetra_device.h"
 #include "tetra_internal.h"
 
@@ -82,8 +84,11 @@ __device__ __forceinline__ float wave_sum(float v) {
 // 2: DOS in the common scale fixed by *gbound, summed exactly into gacc with 64-bit global atomics.
 template <int NORB, typename WT, int MODE>
 __device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
-  constexpr int LC = ((HCAP / NORB) - 1) & ~1;  // energies per histogram pass (even)
-  constexpr int PITCH = LC + 1;  // odd row pitch: the flush reads across orbitals without bank conflicts
+  constexpr int NPAIR = (NORB + 1) / 2;
+  // Histogram rows (one per orbital pair in the packed form, one per orbital in the wide form) have a
+  // fixed, odd stride in 64-bit words: the row offsets of a deposit are immediates, and the flush
+  // reads across rows without bank conflicts.
+  constexpr int RSP = (HCAP / NPAIR - 1) | 1, RSW = (HCAP / NORB - 1) | 1;
   __shared__ float s_eps[NPMAX];
   __shared__ float s_w[NPMAX * NORB];
   __shared__ unsigned long long s_hist[HCAP];
@@ -198,8 +203,15 @@ __device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
   if (MODE == 2) B = 1.0001f * *a.gbound;  // margin for the rounding of the float sum
   if (!(B > 0.0f)) return;  // nothing to add (uniform across the block)
   const bool packed = MODE == 0 && bmin >= 0.0f && Bn <= 0.5f * B;  // uniform across the block
-  constexpr int NPAIR = (NORB + 1) / 2;
-  const int rows = packed ? NPAIR : NORB;  // histogram rows of 64-bit words
+  const int rows = packed ? NPAIR : NORB;
+  const int RS = packed ? RSP : RSW;
+  // Copies: lane l adds into copy l % CP of a bin (each bin's copies are adjacent words), so the lanes
+  // of neighbouring cubes, which usually hit the same bins at the same time, do not serialise on one
+  // LDS address. As many copies (up to four) as keep the tile-band's energy range in one pass.
+  const int span = J1 - J0 + 1;
+  const int cpl = span <= (RS >> 2) ? 2 : span <= (RS >> 1) ? 1 : 0;  // log2 of the copy count
+  const int CP = 1 << cpl;
+  const int LC = RS >> cpl;  // bins per pass
   int bexp;
   frexpf(fminf(B, 3.0e38f), &bexp);  // B <= 2^bexp
   const int sexp = min((packed ? 30 : 62) - bexp, 126);
@@ -213,9 +225,10 @@ __device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
   for (int c0 = J0; c0 <= J1; c0 += LC) {
     const int c1 = min(c0 + LC - 1, J1);
     const int L = c1 - c0 + 1;
-    for (int q = tid; q < rows * L; q += NT) {
-      const int r = q / L;
-      s_hist[r * PITCH + (q - r * L)] = 0ull;
+    const int LW = L << cpl;  // words per row in this pass
+    for (int q = tid; q < rows * LW; q += NT) {
+      const int r = q / LW;
+      s_hist[r * RS + (q - r * LW)] = 0ull;
     }
     __syncthreads();
     if (valid) {
@@ -251,7 +264,7 @@ __device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
         // (the weights are, and the corner weights are clamped at zero against rounding), so the
         // truncating conversion of 0.5 + v rounds v to the nearest integer (halves up).
         auto deposit = [&](int j, const float g[4]) {
-          unsigned long long* h = &s_hist[j - c0];
+          unsigned long long* h = &s_hist[((j - c0) << cpl) + (tid & (CP - 1))];
           if (packed) {
 #pragma unroll
             for (int pr = 0; pr < NPAIR; ++pr) {
@@ -268,13 +281,13 @@ __device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
                 v1 = __builtin_fmaf(g[3], bb[3][m1], v1);
                 word |= (unsigned long long)(unsigned)v1 << 32;
               }
-              atomicAdd(&h[pr * PITCH], word);
+              atomicAdd(&h[pr * RSP], word);
             }
           } else {
 #pragma unroll
             for (int m = 0; m < NORB; ++m) {
               const float v = g[0] * bb[0][m] + g[1] * bb[1][m] + g[2] * bb[2][m] + g[3] * bb[3][m];
-              atomicAdd(&h[m * PITCH], (unsigned long long)__float2ll_rn(v));
+              atomicAdd(&h[m * RSW], (unsigned long long)__float2ll_rn(v));
             }
           }
         };
@@ -286,14 +299,14 @@ __device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
         }
         for (int j = jA + 1; j <= jB; ++j) {
           float g[4];
-          corner_dos_B(cs, local_x(cs, j, a.de), g);
+          corner_dos_B(cs, local_z(cs, j, a.de), g);
 #pragma unroll
           for (int l = 0; l < 4; ++l) g[l] = fmaxf(g[l], 0.0f);
           deposit(j, g);
         }
         for (int j = jB + 1; j <= jhi; ++j) {
           float g[4];
-          corner_dos_C(cs, local_x(cs, j, a.de), g);
+          corner_dos_C(cs, local_y(cs, j, a.de), g);
           g[3] = fmaxf(g[3], 0.0f);
           deposit(j, g);
         }
@@ -303,11 +316,17 @@ __device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
     for (int q = tid; q < L * NORB; q += NT) {
       const int r = q / NORB, m = q - r * NORB;
       const int row = packed ? (m >> 1) : m;
-      const unsigned long long w = s_hist[row * PITCH + r];
+      const unsigned long long* hw = &s_hist[row * RS + (r << cpl)];
       if (MODE == 2) {
+        unsigned long long w = 0ull;
+        for (int c = 0; c < CP; ++c) w += hw[c];
         if (w != 0ull) atomicAdd(&a.gacc[(int64_t)(c0 + r) * NORB + m], w);
       } else {
-        const double sum = packed ? (double)(unsigned)((m & 1) ? (w >> 32) : (w & 0xffffffffull)) : (double)(long long)w;
+        double sum = 0.0;
+        for (int c = 0; c < CP; ++c) {
+          const unsigned long long w = hw[c];
+          sum += packed ? (double)(unsigned)((m & 1) ? (w >> 32) : (w & 0xffffffffull)) : (double)(long long)w;
+        }
         if (sum != 0.0) atomic_add_global(&a.dos[(int64_t)(c0 + r) * NORB + m], (float)(sum * inv_S));
       }
     }
@@ -406,19 +425,25 @@ hipError_t launch_batched(const BatchArgs& b, bool half, hipStream_t s) {
   hipLaunchKernelGGL(batched_zero_kernel, dim3(64, b.n), dim3(256), 0, s, b, NORB);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  static int per_cu[2] = {0, 0};
-  static int cus = 0;
+  // Persistent grid: resident workgroups per CU times the CU count of the current device (cached
+  // per device and weight type; concurrent first calls store the same values).
+  constexpr int kDevCache = 64;
+  static std::atomic<int> cache_cus[kDevCache], cache_occ[kDevCache][2];
+  int dev = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  const bool cached = dev >= 0 && dev < kDevCache;
+  int cus = cached ? cache_cus[dev].load(std::memory_order_relaxed) : 0;
   if (!cus) {
-    int dev = 0;
-    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    if (cached) cache_cus[dev].store(cus, std::memory_order_relaxed);
   }
-  int& occ = per_cu[half ? 1 : 0];
+  int occ = cached ? cache_occ[dev][half ? 1 : 0].load(std::memory_order_relaxed) : 0;
   if (!occ) {
     e = half ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, dos_batched_kernel<NORB, _Float16>, NT, 0)
              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, dos_batched_kernel<NORB, float>, NT, 0);
     if (e != hipSuccess) return e;
     if (occ < 1) occ = 1;
+    if (cached) cache_occ[dev][half ? 1 : 0].store(occ, std::memory_order_relaxed);
   }
   const int grid = std::min(b.total, occ * cus);
   if (half)

@@ -1,0 +1,46 @@
+"""The kernels' per-tetrahedron arithmetic (``tetra_device.h``: sort, windows, case split, corner weights
+in their local frames, and the moment forms of the adjoint) built for the host with g++ and checked
+against the FP64 oracle's corner weights and dual-number energy derivatives on random tetrahedra,
+generic and with nearly equal corner energies. No GPU needed; the harness is test code only.
+
+Bounds (FP32 arithmetic against FP64): corner weights within 1e-5 of the tetrahedron's largest
+weight; the gradient of sum_j sum_l s_l g_l(E_j) over a case range within 1e-4 of the sum of the
+per-energy |derivatives| (a sign or index mistake in any term gives O(1))."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1710_10789_amd", "csrc")
+HARNESS = os.path.join(ROOT, "tests", "host", "device_math_check.cpp")
+
+
+@pytest.fixture(scope="module")
+def harness(tmp_path_factory, oracle_lib):
+    if shutil.which("g++") is None or not os.path.isdir("/opt/rocm/include"):
+        pytest.skip("needs g++ and the ROCm headers")
+    exe = str(tmp_path_factory.mktemp("dmc") / "device_math_check")
+    odir = os.path.dirname(oracle_lib.build())
+    cmd = ["g++", "-O2", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I", CSRC, HARNESS,
+           "-o", exe, "-L", odir, "-ltetra_oracle", f"-Wl,-rpath,{odir}"]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    assert res.returncode == 0, res.stderr[-2000:]
+    return exe
+
+
+def test_corner_weights_and_moment_adjoint_against_oracle(harness):
+    res = subprocess.run([harness, "20000"], capture_output=True, text=True, timeout=600)
+    assert res.returncode == 0, res.stderr
+    rows = {}
+    for line in res.stdout.split("\n"):
+        parts = line.split()
+        if len(parts) == 5:
+            rows[parts[0]] = (int(parts[1]), *map(float, parts[2:]))
+    print(res.stdout)
+    assert set(rows) == {"first", "middle", "third"}
+    for case, (n, werr, gen, deg) in rows.items():
+        assert n > 1000, case
+        assert werr <= 1e-5, (case, werr)
+        assert gen <= 1e-4 and deg <= 1e-4, (case, gen, deg)
