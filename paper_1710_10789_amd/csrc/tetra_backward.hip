@@ -161,82 +161,87 @@ __global__ __launch_bounds__(NT) void dos_backward_kernel(BwdArgs a) {
         {
           {
             {
-              float bb[4][NORB];
-#pragma unroll
-              for (int l = 0; l < 4; ++l) {
-#pragma unroll
-                for (int m = 0; m < NORB; ++m) bb[l][m] = s_w[pt[l] * NORB + m];
-              }
               // Per-case sub-loops (see the forward kernel): no divergence between energy cases.
               int jA, jB;
               case_split(cs, a.de, a.inv_de, jlo, jhi, jA, jB);
               if (!any) jA = jB = jhi;
-              auto load = [&](int j, float Gm[NORB], float sl[4]) {
+              // Every corner weight is a cubic in the range's local variable t, g_l(t) = sum_k c_lk t^k,
+              // so over a case range both the weight gradient sum_j G[j][m] g_l(t_j) and the moments
+              // sum_j s_l(t_j) t_j^k of the energy gradient (s_l = sum_m G b_l) are contractions of the
+              // power sums H_k[m] = sum_j G[j][m] t_j^k: the loop over energies accumulates only those.
+              auto rowG = [&](int j, float Gm[NORB]) {
                 const float* Gj = &s_G[(j - c0) * NORB];
 #pragma unroll
                 for (int m = 0; m < NORB; ++m) Gm[m] = Gj[m];
-#pragma unroll
-                for (int l = 0; l < 4; ++l) {
-                  float acc = 0.0f;
-#pragma unroll
-                  for (int m = 0; m < NORB; ++m) acc += Gm[m] * bb[l][m];
-                  sl[l] = acc;
-                }
               };
-              auto accumulate = [&](const float Gm[NORB], const float g[4]) {
-#pragma unroll
-                for (int l = 0; l < 4; ++l)
-#pragma unroll
-                  for (int m = 0; m < NORB; ++m) gb[l][m] += Gm[m] * g[l];
-              };
+              const float* const brow[4] = {&s_w[pt[0] * NORB], &s_w[pt[1] * NORB], &s_w[pt[2] * NORB],
+                                            &s_w[pt[3] * NORB]};
               auto add_eb = [&](const float Eb[4]) {
 #pragma unroll
                 for (int l = 0; l < 4; ++l) ge[l][0] += Eb[l];
               };
-              if (jA >= jlo) {
-                float m[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+              if (jA >= jlo) {  // first case, t = x: powers 1..3
+                float H[3][NORB];
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                  for (int m = 0; m < NORB; ++m) H[k][m] = 0.0f;
                 for (int j = jlo; j <= jA; ++j) {
-                  float Gm[NORB], sl[4], g[4];
-                  load(j, Gm, sl);
-                  const float x = local_x(cs, j, a.de);
-                  corner_dos_A(cs, x, g);
-                  corner_dos_moments_acc_A(x, sl, m);
-                  accumulate(Gm, g);
+                  float Gm[NORB];
+                  rowG(j, Gm);
+                  const float x = local_x(cs, j, a.de), x2 = x * x, x3 = x2 * x;
+#pragma unroll
+                  for (int m = 0; m < NORB; ++m) {
+                    H[0][m] = __builtin_fmaf(Gm[m], x, H[0][m]);
+                    H[1][m] = __builtin_fmaf(Gm[m], x2, H[1][m]);
+                    H[2][m] = __builtin_fmaf(Gm[m], x3, H[2][m]);
+                  }
                 }
                 float Eb[4];
-                corner_dos_moments_finish_A(cs, a.V, m, Eb);
+                adjoint_range_A<NORB>(cs, a.V, brow, H, gb, Eb);
                 add_eb(Eb);
               }
-              if (jB > jA) {
-                float M[4][4];
+              if (jB > jA) {  // middle case, t = z: powers 0..3
+                float H[4][NORB];
 #pragma unroll
-                for (int l = 0; l < 4; ++l)
+                for (int k = 0; k < 4; ++k)
 #pragma unroll
-                  for (int k = 0; k < 4; ++k) M[l][k] = 0.0f;
+                  for (int m = 0; m < NORB; ++m) H[k][m] = 0.0f;
                 for (int j = jA + 1; j <= jB; ++j) {
-                  float Gm[NORB], sl[4], g[4];
-                  load(j, Gm, sl);
-                  const float z = local_z(cs, j, a.de);
-                  corner_dos_B(cs, z, g);
-                  corner_dos_moments_acc_B(z, sl, M);
-                  accumulate(Gm, g);
+                  float Gm[NORB];
+                  rowG(j, Gm);
+                  const float z = local_z(cs, j, a.de), z2 = z * z, z3 = z2 * z;
+#pragma unroll
+                  for (int m = 0; m < NORB; ++m) {
+                    H[0][m] += Gm[m];
+                    H[1][m] = __builtin_fmaf(Gm[m], z, H[1][m]);
+                    H[2][m] = __builtin_fmaf(Gm[m], z2, H[2][m]);
+                    H[3][m] = __builtin_fmaf(Gm[m], z3, H[3][m]);
+                  }
                 }
                 float Eb[4];
-                corner_dos_moments_finish_B(cs, a.V, M, Eb);
+                adjoint_range_B<NORB>(cs, a.V, brow, H, gb, Eb);
                 add_eb(Eb);
               }
-              if (jhi > jB) {
-                float m[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+              if (jhi > jB) {  // third case, t = y: powers 1..3
+                float H[3][NORB];
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                  for (int m = 0; m < NORB; ++m) H[k][m] = 0.0f;
                 for (int j = jB + 1; j <= jhi; ++j) {
-                  float Gm[NORB], sl[4], g[4];
-                  load(j, Gm, sl);
-                  const float y = local_y(cs, j, a.de);
-                  corner_dos_C(cs, y, g);
-                  corner_dos_moments_acc_C(y, sl, m);
-                  accumulate(Gm, g);
+                  float Gm[NORB];
+                  rowG(j, Gm);
+                  const float y = local_y(cs, j, a.de), y2 = y * y, y3 = y2 * y;
+#pragma unroll
+                  for (int m = 0; m < NORB; ++m) {
+                    H[0][m] = __builtin_fmaf(Gm[m], y, H[0][m]);
+                    H[1][m] = __builtin_fmaf(Gm[m], y2, H[1][m]);
+                    H[2][m] = __builtin_fmaf(Gm[m], y3, H[2][m]);
+                  }
                 }
                 float Eb[4];
-                corner_dos_moments_finish_C(cs, a.V, m, Eb);
+                adjoint_range_C<NORB>(cs, a.V, brow, H, gb, Eb);
                 add_eb(Eb);
               }
             }

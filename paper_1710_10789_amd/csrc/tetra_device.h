@@ -7,9 +7,9 @@
 //       g1 = 4 K x^2 (3 - x S),   g_l = 4 K x^3 / E_l1  (l = 2, 3, 4)
 //   third case (E3 < E < E4), y = E4 - E, K' = V / (E41 E42 E43), S' = 1/E41 + 1/E42 + 1/E43:
 //       g_l = 4 K' y^3 / E_4l  (l = 1, 2, 3),   g4 = 4 K' y^2 (3 - y S')
-//   middle case (E2 < E <= E3): the printed C1, C2, C3 and their derivatives with z = E - E2,
-//       q = E3 - E, p = E4 - E, and the last term of dw3/dE taken as (C2 + C3)/E32, the form
-//       that is the energy derivative of the printed w3.
+//   middle case (E2 < E <= E3), z = E - E2: the printed C1, C2, C3 and their derivatives, with the
+//       last term of dw3/dE taken as (C2 + C3)/E32 (the energy derivative of the printed w3),
+//       expanded as cubics in z (coefficients at corner_dos_B_coeffs).
 //
 // with V = V_T / (4 V_G). Energies are handled in local frames: x = E_j - E1 (z = E_j - E2 in the
 // middle case, y = E4 - E_j in the third) is formed per (tetrahedron, band, j) from e0 - E1 (e0 - E2,
@@ -173,19 +173,41 @@ __host__ __device__ __forceinline__ void corner_dos_A(const TetSetup& c, float x
   g[3] = u * c.r41;
 }
 
-__host__ __device__ __forceinline__ void corner_dos_B(const TetSetup& c, float z, float g[4]) {
-  // x = E - E1, q = E3 - E, p = E4 - E from z = E - E2 and differences to E2: q and p are divided by
-  // E32 and E42 below, so they are formed where those differences are exact for close energies.
-  const float x = z + c.e21, q = c.e32 - z, p = c.e42 - z;
-  const float C1 = c.k1 * x * x, dC1 = 2.0f * c.k1 * x;
-  const float C2 = c.k2 * x * z * q, dC2 = c.k2 * (x * q + z * q - x * z);
-  const float C3 = c.k3 * z * z * p, dC3 = c.k3 * z * (2.0f * p - z);
-  const float S12 = C1 + C2, D12 = dC1 + dC2, S23 = C2 + C3, D23 = dC2 + dC3;
-  const float S123 = S12 + C3, D123 = D12 + dC3;
-  g[0] = dC1 + (D12 * q - S12) * c.r31 + (D123 * p - S123) * c.r41;
-  g[1] = D123 + (D23 * q - S23) * c.r32 + (dC3 * p - C3) * c.r42;
-  g[2] = (D12 * x + S12) * c.r31 + (D23 * z + S23) * c.r32;
-  g[3] = (D123 * x + S123) * c.r41 + (dC3 * z + C3) * c.r42;
+// Middle case. On (E2, E3] every corner weight is a cubic in z = E - E2, g_l(z) = sum_k c_lk z^k, with
+// coefficients in a = E21, b = E32, c = E42 and k1 = V/(E31 E41) (the expansion of the printed formulas):
+//   g1: 4 a k1 (ab + ac + 2bc) / (E31 E41),  -12 k1 (a^2 - bc) / (E31 E41),  -12 k1 (2a + b + c) / (E31 E41),
+//       4 k1 (a^2 + 2ab + 2ac + b^2 + bc + c^2) / (b c E31 E41)
+//   g2: 4 a k1,  12 k1,  -12 k1 (a + b + c) / (b c),  4 k1 (ab + ac + b^2 + bc + c^2) / (b^2 c^2)
+//   g3: 4 a^2 k1 / E31,  12 a k1 / E31,  12 k1 / E31,  -4 k1 (a^2 + 2ab + ac + b^2 + 2bc) / (b^2 c E31)
+//   g4: 4 a^2 k1 / E41,  12 a k1 / E41,  12 k1 / E41,  -4 k1 (a^2 + ab + 2ac + 2bc + c^2) / (b c^2 E41)
+// coef[l][k] is the z^k coefficient of g_{l+1}.
+__host__ __device__ __forceinline__ void corner_dos_B_coeffs(const TetSetup& c, float V, float coef[4][4]) {
+  const float a = c.e21, b = c.e32, cc = c.e42;
+  const float rb = c.r32, rc = c.r42, rbc = rb * rc;
+  const float k1 = V * c.r31 * c.r41, k31 = k1 * c.r31, k41 = k1 * c.r41, k3141 = k31 * c.r41;
+  const float ab = a * b, ac = a * cc, bc = b * cc, aa = a * a, bb = b * b, c2 = cc * cc;
+  coef[0][0] = 4.0f * a * (ab + ac + 2.0f * bc) * k3141;
+  coef[0][1] = -12.0f * (aa - bc) * k3141;
+  coef[0][2] = -12.0f * (2.0f * a + b + cc) * k3141;
+  coef[0][3] = 4.0f * (aa + 2.0f * ab + 2.0f * ac + bb + bc + c2) * rbc * k3141;
+  coef[1][0] = 4.0f * a * k1;
+  coef[1][1] = 12.0f * k1;
+  coef[1][2] = -12.0f * (a + b + cc) * rbc * k1;
+  coef[1][3] = 4.0f * (ab + ac + bb + bc + c2) * rbc * rbc * k1;
+  coef[2][0] = 4.0f * aa * k31;
+  coef[2][1] = 12.0f * a * k31;
+  coef[2][2] = 12.0f * k31;
+  coef[2][3] = -4.0f * (aa + 2.0f * ab + ac + bb + 2.0f * bc) * rb * rbc * k31;
+  coef[3][0] = 4.0f * aa * k41;
+  coef[3][1] = 12.0f * a * k41;
+  coef[3][2] = 12.0f * k41;
+  coef[3][3] = -4.0f * (aa + ab + 2.0f * ac + 2.0f * bc + c2) * rc * rbc * k41;
+}
+
+__host__ __device__ __forceinline__ void corner_dos_B_poly(const float coef[4][4], float z, float g[4]) {
+#pragma unroll
+  for (int l = 0; l < 4; ++l)
+    g[l] = __builtin_fmaf(__builtin_fmaf(__builtin_fmaf(coef[l][3], z, coef[l][2]), z, coef[l][1]), z, coef[l][0]);
 }
 
 __host__ __device__ __forceinline__ void corner_dos_C(const TetSetup& c, float y, float g[4]) {
@@ -197,28 +219,15 @@ __host__ __device__ __forceinline__ void corner_dos_C(const TetSetup& c, float y
   g[3] = t * (3.0f - y * c.sC);
 }
 
-// Adjoint of the corner weights by moments. For multipliers s_l (one per sorted corner) summed over the
-// energies of one case range, F = sum_j sum_l s_l g_l(E_j) is a combination of a few moments
-// sum_j s_l t_j^k of the range's local variable t (x = E - E1 in the first case, y = E4 - E in the
-// third, z = E - E2 in the middle one), because every corner weight is a polynomial in t on its case
-// range. The per-energy work is the moments (*_acc); the derivative of F with respect to the four
-// sorted corner energies at fixed E_j is taken once per range through the per-tetrahedron constants
-// (*_finish), in reverse.
+// Adjoint of the corner weights by moments. For multipliers s_l (one per sorted corner), summed over the
+// energies of one case range, F = sum_j sum_l s_l g_l(E_j) is a combination of the moments
+// sum_j s_l t_j^k of the range's local variable t (x = E - E1 in the first case, z = E - E2 in the
+// middle one, y = E4 - E in the third), because every corner weight is a cubic in t on its range.
+// The *_finish functions take the derivative of F with respect to the four sorted corner energies at
+// fixed E_j from the moments, in reverse through the per-tetrahedron constants.
 
 // First case: g1 = 4K x^2 (3 - x S), g_l = 4K x^3 r_l1 (l = 2, 3, 4), K = V r21 r31 r41, S = r21 + r31 + r41.
-// Moments m[9]: s1 x, s1 x^2, s1 x^3, s_l x^2 (l = 2, 3, 4), s_l x^3 (l = 2, 3, 4).
-__host__ __device__ __forceinline__ void corner_dos_moments_acc_A(float x, const float s[4], float m[9]) {
-  const float x2 = x * x, x3 = x2 * x;
-  m[0] = __builtin_fmaf(s[0], x, m[0]);
-  m[1] = __builtin_fmaf(s[0], x2, m[1]);
-  m[2] = __builtin_fmaf(s[0], x3, m[2]);
-#pragma unroll
-  for (int l = 1; l < 4; ++l) {
-    m[2 + l] = __builtin_fmaf(s[l], x2, m[2 + l]);
-    m[5 + l] = __builtin_fmaf(s[l], x3, m[5 + l]);
-  }
-}
-
+// Moments m[9] (sums over the range): s1 x, s1 x^2, s1 x^3, s_l x^2 (l = 2, 3, 4), s_l x^3 (l = 2, 3, 4).
 __host__ __device__ __forceinline__ void corner_dos_moments_finish_A(const TetSetup& c, float V, const float m[9], float Eb[4]) {
   // F = 4K T, T = 3 sum s1 x^2 - S sum s1 x^3 + sum_l r_l1 sum s_l x^3
   const float T = 3.0f * m[1] - c.sA * m[2] + c.r21 * m[6] + c.r31 * m[7] + c.r41 * m[8];
@@ -238,18 +247,6 @@ __host__ __device__ __forceinline__ void corner_dos_moments_finish_A(const TetSe
 // Third case (mirror of the first, y = E4 - E): g_l = 4K' y^3 r_4l (l = 1, 2, 3), g4 = 4K' y^2 (3 - y S'),
 // K' = V r41 r42 r43, S' = r41 + r42 + r43. Moments m[9]: s4 y, s4 y^2, s4 y^3, s_l y^2 (l = 1, 2, 3),
 // s_l y^3 (l = 1, 2, 3).
-__host__ __device__ __forceinline__ void corner_dos_moments_acc_C(float y, const float s[4], float m[9]) {
-  const float y2 = y * y, y3 = y2 * y;
-  m[0] = __builtin_fmaf(s[3], y, m[0]);
-  m[1] = __builtin_fmaf(s[3], y2, m[1]);
-  m[2] = __builtin_fmaf(s[3], y3, m[2]);
-#pragma unroll
-  for (int l = 0; l < 3; ++l) {
-    m[3 + l] = __builtin_fmaf(s[l], y2, m[3 + l]);
-    m[6 + l] = __builtin_fmaf(s[l], y3, m[6 + l]);
-  }
-}
-
 __host__ __device__ __forceinline__ void corner_dos_moments_finish_C(const TetSetup& c, float V, const float m[9], float Eb[4]) {
   const float T = 3.0f * m[1] - c.sC * m[2] + c.r41 * m[6] + c.r42 * m[7] + c.r43 * m[8];
   const float K4 = 4.0f * c.kC, V4T = 4.0f * V * T;
@@ -265,30 +262,7 @@ __host__ __device__ __forceinline__ void corner_dos_moments_finish_C(const TetSe
   Eb[3] = e41b + e42b + e43b + Fy;
 }
 
-// Middle case by moments. On (E2, E3] every corner weight is a cubic in z = E - E2,
-//   g_l(z) = sum_k c_lk z^k,
-// whose coefficients are rational functions of a = E21, b = E32, c = E42 (with k1 = V/(E31 E41)):
-//   g1: 4 a k1 (ab + ac + 2bc) / (E31 E41),  -12 k1 (a^2 - bc) / (E31 E41),  -12 k1 (2a + b + c) / (E31 E41),
-//       4 k1 (a^2 + 2ab + 2ac + b^2 + bc + c^2) / (b c E31 E41)
-//   g2: 4 a k1,  12 k1,  -12 k1 (a + b + c) / (b c),  4 k1 (ab + ac + b^2 + bc + c^2) / (b^2 c^2)
-//   g3: 4 a^2 k1 / E31,  12 a k1 / E31,  12 k1 / E31,  -4 k1 (a^2 + 2ab + ac + b^2 + 2bc) / (b^2 c E31)
-//   g4: 4 a^2 k1 / E41,  12 a k1 / E41,  12 k1 / E41,  -4 k1 (a^2 + ab + 2ac + 2bc + c^2) / (b c^2 E41)
-// (the expansion of the printed middle-case formulas, with the corrected last term of dw3/dE). Over a
-// range of energies, sum_j sum_l s_l g_l(z_j) = sum_lk c_lk M_lk with the moments M_lk = sum_j s_l z_j^k,
-// so the gradient with respect to the corner energies needs only the 16 moments per range: the
-// per-energy work is the moments, and the derivative through the coefficients is taken once, in
-// reverse, by corner_dos_moments_finish_B.
-__host__ __device__ __forceinline__ void corner_dos_moments_acc_B(float z, const float s[4], float M[4][4]) {
-  const float z2 = z * z, z3 = z2 * z;
-#pragma unroll
-  for (int l = 0; l < 4; ++l) {
-    M[l][0] += s[l];
-    M[l][1] = __builtin_fmaf(s[l], z, M[l][1]);
-    M[l][2] = __builtin_fmaf(s[l], z2, M[l][2]);
-    M[l][3] = __builtin_fmaf(s[l], z3, M[l][3]);
-  }
-}
-
+// Middle case: the 16 moments M_lk = sum_j s_l z_j^k (k = 0..3) give F = sum_lk c_lk M_lk.
 __host__ __device__ __forceinline__ void corner_dos_moments_finish_B(const TetSetup& c, float V, const float M[4][4],
                                                                      float Eb[4]) {
   const float a = c.e21, b = c.e32, cc = c.e42;
@@ -370,6 +344,78 @@ __host__ __device__ __forceinline__ void corner_dos_moments_finish_B(const TetSe
   Eb[1] = ab_ - bb_ - cb_ - Fz;
   Eb[2] = bb_;
   Eb[3] = cb_;
+}
+
+// Range ends of the adjoint. Over the energies of one case range with local variable t, the loop
+// accumulates only the power sums H_k[m] = sum_j G[j][m] t_j^k of the loss gradient G. Then, with
+// b[l] the orbital weights of sorted corner l and g_l(t) = sum_k c_lk t^k,
+//   dL/db_l[m] += sum_k c_lk H_k[m]                      (the weight gradient)
+//   moments    sum_j s_l(t_j) t_j^k = sum_m b_l[m] H_k[m] (s_l = sum_m G b_l, for the energy gradient)
+// and Eb gets the range's derivative with respect to the four sorted corner energies.
+template <int NORB>
+__host__ __device__ __forceinline__ float dot_row(const float* b, const float h[NORB]) {
+  float acc = 0.0f;
+#pragma unroll
+  for (int m = 0; m < NORB; ++m) acc = __builtin_fmaf(b[m], h[m], acc);
+  return acc;
+}
+
+// First case, t = x = E - E1, H[0..2] = powers 1..3.
+template <int NORB>
+__host__ __device__ __forceinline__ void adjoint_range_A(const TetSetup& c, float V, const float* const b[4],
+                                                         const float H[3][NORB], float gb[4][NORB], float Eb[4]) {
+  const float mo[9] = {dot_row<NORB>(b[0], H[0]), dot_row<NORB>(b[0], H[1]), dot_row<NORB>(b[0], H[2]),
+                       dot_row<NORB>(b[1], H[1]), dot_row<NORB>(b[2], H[1]), dot_row<NORB>(b[3], H[1]),
+                       dot_row<NORB>(b[1], H[2]), dot_row<NORB>(b[2], H[2]), dot_row<NORB>(b[3], H[2])};
+  corner_dos_moments_finish_A(c, V, mo, Eb);
+  // g1 = 12 K x^2 - 4 K S x^3, g_l = 4 K r_l1 x^3
+  const float c12 = 12.0f * c.kA, c13 = -4.0f * c.kA * c.sA, k4 = 4.0f * c.kA;
+  const float c3[3] = {k4 * c.r21, k4 * c.r31, k4 * c.r41};
+#pragma unroll
+  for (int m = 0; m < NORB; ++m) {
+    gb[0][m] = __builtin_fmaf(c12, H[1][m], __builtin_fmaf(c13, H[2][m], gb[0][m]));
+#pragma unroll
+    for (int l = 1; l < 4; ++l) gb[l][m] = __builtin_fmaf(c3[l - 1], H[2][m], gb[l][m]);
+  }
+}
+
+// Middle case, t = z = E - E2, H[0..3] = powers 0..3.
+template <int NORB>
+__host__ __device__ __forceinline__ void adjoint_range_B(const TetSetup& c, float V, const float* const b[4],
+                                                         const float H[4][NORB], float gb[4][NORB], float Eb[4]) {
+  float M[4][4];
+#pragma unroll
+  for (int l = 0; l < 4; ++l)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) M[l][k] = dot_row<NORB>(b[l], H[k]);
+  corner_dos_moments_finish_B(c, V, M, Eb);
+  float coef[4][4];
+  corner_dos_B_coeffs(c, V, coef);
+#pragma unroll
+  for (int l = 0; l < 4; ++l)
+#pragma unroll
+    for (int m = 0; m < NORB; ++m)
+      gb[l][m] += __builtin_fmaf(coef[l][3], H[3][m],
+                                 __builtin_fmaf(coef[l][2], H[2][m], __builtin_fmaf(coef[l][1], H[1][m], coef[l][0] * H[0][m])));
+}
+
+// Third case, t = y = E4 - E, H[0..2] = powers 1..3.
+template <int NORB>
+__host__ __device__ __forceinline__ void adjoint_range_C(const TetSetup& c, float V, const float* const b[4],
+                                                         const float H[3][NORB], float gb[4][NORB], float Eb[4]) {
+  const float mo[9] = {dot_row<NORB>(b[3], H[0]), dot_row<NORB>(b[3], H[1]), dot_row<NORB>(b[3], H[2]),
+                       dot_row<NORB>(b[0], H[1]), dot_row<NORB>(b[1], H[1]), dot_row<NORB>(b[2], H[1]),
+                       dot_row<NORB>(b[0], H[2]), dot_row<NORB>(b[1], H[2]), dot_row<NORB>(b[2], H[2])};
+  corner_dos_moments_finish_C(c, V, mo, Eb);
+  // g_l = 4 K' r_4l y^3 (l = 1, 2, 3), g4 = 12 K' y^2 - 4 K' S' y^3
+  const float c42 = 12.0f * c.kC, c43 = -4.0f * c.kC * c.sC, k4 = 4.0f * c.kC;
+  const float c3[3] = {k4 * c.r41, k4 * c.r42, k4 * c.r43};
+#pragma unroll
+  for (int m = 0; m < NORB; ++m) {
+    gb[3][m] = __builtin_fmaf(c42, H[1][m], __builtin_fmaf(c43, H[2][m], gb[3][m]));
+#pragma unroll
+    for (int l = 0; l < 3; ++l) gb[l][m] = __builtin_fmaf(c3[l], H[2][m], gb[l][m]);
+  }
 }
 
 // Estimate of the window of grid indices j with E1 < E_j < E4, clipped to [lo, hi] (empty when

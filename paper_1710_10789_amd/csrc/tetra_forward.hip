@@ -297,9 +297,11 @@ __device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
           g[0] = fmaxf(g[0], 0.0f);  // g[1..3] are products of non-negative factors
           deposit(j, g);
         }
+        float coef[4][4];
+        if (jB > jA) corner_dos_B_coeffs(cs, a.V, coef);
         for (int j = jA + 1; j <= jB; ++j) {
           float g[4];
-          corner_dos_B(cs, local_z(cs, j, a.de), g);
+          corner_dos_B_poly(coef, local_z(cs, j, a.de), g);
 #pragma unroll
           for (int l = 0; l < 4; ++l) g[l] = fmaxf(g[l], 0.0f);
           deposit(j, g);
@@ -372,7 +374,7 @@ struct BatchArgs {
 };
 
 template <int NORB, typename WT>
-__global__ __launch_bounds__(NT) void dos_batched_kernel(BatchArgs b) {
+__global__ __launch_bounds__(NT, NORB <= 8 ? 5 : 2) void dos_batched_kernel(BatchArgs b) {
   __shared__ int s_unit;
   for (;;) {
     __syncthreads();  // the previous unit's LDS reads are done

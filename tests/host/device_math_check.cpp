@@ -2,15 +2,19 @@
 // corner weights and their dual-number energy derivatives. Test harness only: compiled by
 // tests/test_device_math_host.py with g++ and linked with the oracle library.
 //
-// For random tetrahedra (generic and with nearly equal corner energies) on an equidistant energy grid:
-//  * corner weights of every in-window energy, per case, against the oracle's;
-//  * per case range, the gradient of sum_j sum_l s_l g_l(E_j) with respect to the four sorted corner
-//    energies from the moment forms (*_acc per energy, *_finish per range) against the sum of the
-//    oracle's per-energy derivatives.
-// Prints one line per case: max weight error (relative to the tetrahedron's largest weight) and max
-// gradient error (relative to the sum of the per-energy |derivatives| of the range).
+// For random tetrahedra (generic, and with one pair of neighbouring corner energies within 1e-3) on
+// an equidistant energy grid, with random loss gradients G[j][m] and orbital weights b_l[m]:
+//  * the corner weights of every in-window energy, per case (the middle case in its cubic form),
+//    against the oracle's;
+//  * per case range, the adjoint as the kernel forms it: power sums H_k[m] = sum_j G[j][m] t_j^k over
+//    the range, then adjoint_range_* for the weight gradient sum_j G[j][m] g_l(E_j) and the energy
+//    gradient sum_j sum_l s_l dg_l/dE_i (s_l = sum_m G[j][m] b_l[m]), against the oracle's sums.
+// Prints one line per case: ranges, max weight error (relative to the tetrahedron's largest weight),
+// max energy-gradient error (relative to the range's sum of per-energy |derivatives|) for generic and
+// nearly degenerate tetrahedra, and max weight-gradient error (relative to sum_j |G| |g|).
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <random>
 
 #include "tetra_device.h"
@@ -20,12 +24,14 @@ extern "C" void tetra_oracle_corner_weights_grad(const double e_sorted[4], doubl
 
 using namespace tetra;
 
+constexpr int NO = 3;  // orbitals
+
 int main(int argc, char** argv) {
   const int n = argc > 1 ? std::atoi(argv[1]) : 100000;
   std::mt19937 rng(11);
-  std::uniform_real_distribution<float> U(-1.0f, 1.0f);
+  std::uniform_real_distribution<float> U(-1.0f, 1.0f), P(0.0f, 1.0f);
   const float V = 1.0e-3f, e0 = -1.5f, de = 3.0f / 1999.0f;
-  double werr[3] = {0, 0, 0}, gerr[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  double werr[3] = {0, 0, 0}, eerr[3][2] = {{0, 0}, {0, 0}, {0, 0}}, berr[3] = {0, 0, 0};
   long ranges[3] = {0, 0, 0};
   for (int it = 0; it < n; ++it) {
     float e[4];
@@ -42,60 +48,86 @@ int main(int argc, char** argv) {
     if (jlo > jhi) continue;
     int jA, jB;
     case_split(cs, de, 1.0f / de, jlo, jhi, jA, jB);
-    const int lo[3] = {jlo, jA + 1, jB + 1}, hi[3] = {jA, jB, jhi};
+    float b[4][NO];
+    for (int l = 0; l < 4; ++l)
+      for (int m = 0; m < NO; ++m) b[l][m] = P(rng);
+    const float* const brow[4] = {b[0], b[1], b[2], b[3]};
     double gmax = 0;
     for (int j = jlo; j <= jhi; ++j) {
       double g[4], dg[16];
       tetra_oracle_corner_weights_grad(ed, (double)e0 + (double)j * de, 4.0 * V, g, dg);
       for (int l = 0; l < 4; ++l) gmax = std::fmax(gmax, std::fabs(g[l]));
     }
+    const int lo[3] = {jlo, jA + 1, jB + 1}, hi[3] = {jA, jB, jhi};
+    float coef[4][4];
+    corner_dos_B_coeffs(cs, V, coef);
     for (int k = 0; k < 3; ++k) {
       if (hi[k] < lo[k]) continue;
-      float m9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-      float M[4][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-      double ref[4] = {0, 0, 0, 0}, scale = 0;
+      float H[4][NO] = {};  // powers 1..3 (first, third case) or 0..3 (middle case)
+      double eref[4] = {0, 0, 0, 0}, escale = 0, bref[4][NO] = {}, bscale = 0;
       for (int j = lo[k]; j <= hi[k]; ++j) {
-        const float s[4] = {U(rng), U(rng), U(rng), U(rng)};
+        float G[NO];
+        for (int m = 0; m < NO; ++m) G[m] = U(rng);
         double g[4], dg[16];
         tetra_oracle_corner_weights_grad(ed, (double)e0 + (double)j * de, 4.0 * V, g, dg);
+        double s[4];
+        for (int l = 0; l < 4; ++l) {
+          s[l] = 0;
+          for (int m = 0; m < NO; ++m) s[l] += (double)G[m] * b[l][m];
+          for (int m = 0; m < NO; ++m) {
+            bref[l][m] += (double)G[m] * g[l];
+            bscale += std::fabs((double)G[m] * g[l]);
+          }
+        }
         for (int i = 0; i < 4; ++i) {
           double acc = 0;
-          for (int l = 0; l < 4; ++l) acc += (double)s[l] * dg[4 * l + i];
-          ref[i] += acc;
-          scale += std::fabs(acc);
+          for (int l = 0; l < 4; ++l) acc += s[l] * dg[4 * l + i];
+          eref[i] += acc;
+          escale += std::fabs(acc);
         }
-        float gk[4];
-        const float x = local_x(cs, j, de);
+        float gk[4], t;
         if (k == 0) {
-          corner_dos_A(cs, x, gk);
-          corner_dos_moments_acc_A(x, s, m9);
+          t = local_x(cs, j, de);
+          corner_dos_A(cs, t, gk);
         } else if (k == 1) {
-          const float z = local_z(cs, j, de);
-          corner_dos_B(cs, z, gk);
-          corner_dos_moments_acc_B(z, s, M);
+          t = local_z(cs, j, de);
+          corner_dos_B_poly(coef, t, gk);
         } else {
-          const float y = local_y(cs, j, de);
-          corner_dos_C(cs, y, gk);
-          corner_dos_moments_acc_C(y, s, m9);
+          t = local_y(cs, j, de);
+          corner_dos_C(cs, t, gk);
         }
         for (int l = 0; l < 4; ++l) werr[k] = std::fmax(werr[k], std::fabs(gk[l] - g[l]) / gmax);
+        const float t2 = t * t, t3 = t2 * t;
+        for (int m = 0; m < NO; ++m) {
+          if (k == 1) {
+            H[0][m] += G[m];
+            H[1][m] = std::fma(G[m], t, H[1][m]);
+            H[2][m] = std::fma(G[m], t2, H[2][m]);
+            H[3][m] = std::fma(G[m], t3, H[3][m]);
+          } else {
+            H[0][m] = std::fma(G[m], t, H[0][m]);
+            H[1][m] = std::fma(G[m], t2, H[1][m]);
+            H[2][m] = std::fma(G[m], t3, H[2][m]);
+          }
+        }
       }
-      float Eb[4];
-      if (k == 0) corner_dos_moments_finish_A(cs, V, m9, Eb);
-      else if (k == 1) corner_dos_moments_finish_B(cs, V, M, Eb);
-      else corner_dos_moments_finish_C(cs, V, m9, Eb);
-      double d = 0;
-      for (int i = 0; i < 4; ++i) {
-        if (!std::isfinite(Eb[i])) d = INFINITY;
-        d = std::fmax(d, std::fabs(Eb[i] - ref[i]));
-      }
-      double& slot = gerr[k][kind == 0 ? 0 : 1];
-      slot = std::fmax(slot, d / scale);
+      float gb[4][NO] = {}, Eb[4];
+      if (k == 0) adjoint_range_A<NO>(cs, V, brow, H, gb, Eb);
+      else if (k == 1) adjoint_range_B<NO>(cs, V, brow, H, gb, Eb);
+      else adjoint_range_C<NO>(cs, V, brow, H, gb, Eb);
+      double de_ = 0, db_ = 0;
+      for (int i = 0; i < 4; ++i) de_ = std::isfinite(Eb[i]) ? std::fmax(de_, std::fabs(Eb[i] - eref[i])) : INFINITY;
+      for (int l = 0; l < 4; ++l)
+        for (int m = 0; m < NO; ++m)
+          db_ = std::isfinite(gb[l][m]) ? std::fmax(db_, std::fabs(gb[l][m] - bref[l][m])) : INFINITY;
+      double& slot = eerr[k][kind == 0 ? 0 : 1];
+      slot = std::fmax(slot, de_ / escale);
+      berr[k] = std::fmax(berr[k], db_ / bscale);
       ++ranges[k];
     }
   }
   const char* names[3] = {"first", "middle", "third"};
   for (int k = 0; k < 3; ++k)
-    std::printf("%s %ld %.6e %.6e %.6e\n", names[k], ranges[k], werr[k], gerr[k][0], gerr[k][1]);
+    std::printf("%s %ld %.6e %.6e %.6e %.6e\n", names[k], ranges[k], werr[k], eerr[k][0], eerr[k][1], berr[k]);
   return 0;
 }
