@@ -161,7 +161,7 @@ __global__ __launch_bounds__(NT) void dos_backward_kernel(BwdArgs a) {
         {
           {
             {
-              // Per-case sub-loops (see the forward kernel): no divergence between energy cases.
+              // One loop per energy case (each case has its own polynomial variable and power sums).
               int jA, jB;
               case_split(cs, a.de, a.inv_de, jlo, jhi, jA, jB);
               if (!any) jA = jB = jhi;

@@ -207,9 +207,9 @@ __device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
   const int RS = packed ? RSP : RSW;
   // Copies: lane l adds into copy l % CP of a bin (each bin's copies are adjacent words), so the lanes
   // of neighbouring cubes, which usually hit the same bins at the same time, do not serialise on one
-  // LDS address. As many copies (up to four) as keep the tile-band's energy range in one pass.
+  // LDS address. As many copies (up to eight) as keep the tile-band's energy range in one pass.
   const int span = J1 - J0 + 1;
-  const int cpl = span <= (RS >> 2) ? 2 : span <= (RS >> 1) ? 1 : 0;  // log2 of the copy count
+  const int cpl = span <= (RS >> 3) ? 3 : span <= (RS >> 2) ? 2 : span <= (RS >> 1) ? 1 : 0;  // log2 of the copy count
   const int CP = 1 << cpl;
   const int LC = RS >> cpl;  // bins per pass
   int bexp;
@@ -256,8 +256,7 @@ __device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
 #pragma unroll
           for (int m = 0; m < NORB; ++m) bb[l][m] = s_w[pt[l] * NORB + m];
         }
-        // The window splits into the three energy cases; each sub-loop runs one case only, so lanes of
-        // a wavefront do not execute the other cases' code.
+        // The window splits into the three energy cases at jA and jB.
         int jA, jB;
         case_split(cs, a.de, a.inv_de, jlo, jhi, jA, jB);
         // Packed: two orbitals per 64-bit word as unsigned 32-bit fields; every term is non-negative
@@ -291,25 +290,23 @@ __device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
             }
           }
         };
-        for (int j = jlo; j <= jA; ++j) {
-          float g[4];
-          corner_dos_A(cs, local_x(cs, j, a.de), g);
-          g[0] = fmaxf(g[0], 0.0f);  // g[1..3] are products of non-negative factors
-          deposit(j, g);
-        }
+        // One loop over the whole window: a wavefront runs as long as its longest window instead of
+        // the sum of its longest per-case ranges; each energy evaluates its own case's weights.
         float coef[4][4];
         if (jB > jA) corner_dos_B_coeffs(cs, a.V, coef);
-        for (int j = jA + 1; j <= jB; ++j) {
+        for (int j = jlo; j <= jhi; ++j) {
           float g[4];
-          corner_dos_B_poly(coef, local_z(cs, j, a.de), g);
+          if (j <= jA) {
+            corner_dos_A(cs, local_x(cs, j, a.de), g);
+            g[0] = fmaxf(g[0], 0.0f);  // g[1..3] are products of non-negative factors
+          } else if (j <= jB) {
+            corner_dos_B_poly(coef, local_z(cs, j, a.de), g);
 #pragma unroll
-          for (int l = 0; l < 4; ++l) g[l] = fmaxf(g[l], 0.0f);
-          deposit(j, g);
-        }
-        for (int j = jB + 1; j <= jhi; ++j) {
-          float g[4];
-          corner_dos_C(cs, local_y(cs, j, a.de), g);
-          g[3] = fmaxf(g[3], 0.0f);
+            for (int l = 0; l < 4; ++l) g[l] = fmaxf(g[l], 0.0f);
+          } else {
+            corner_dos_C(cs, local_y(cs, j, a.de), g);
+            g[3] = fmaxf(g[3], 0.0f);
+          }
           deposit(j, g);
         }
       }

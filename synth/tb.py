@@ -157,6 +157,8 @@ CONFIGS = {
     "k128_b16_e2000": dict(grid=(128, 128, 128), norb=16, ne=2000, seed=0),
     # differentiation case: 64^3 grid, 8 orbitals/bands, 500 energies, target model seed 1
     "k64_b8_e500_fit": dict(grid=(64, 64, 64), norb=8, ne=500, seed=0, target_seed=1),
+    # the paper's largest benchmark shape (60 x 60 x 10 k-points, 8 bands, 1024 energies), context only
+    "k60x60x10_b8_e1024": dict(grid=(60, 60, 10), norb=8, ne=1024, seed=0),
 }
 
 
