@@ -22,6 +22,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -44,13 +45,25 @@ KERNEL_SOURCES = {
 }
 
 
-def kernel_source_hash(kernel: str) -> str:
-    """Hash of the sources a kernel is built from; a traffic record is used only while it matches."""
+def _code_only(text: str) -> str:
+    """C++ source without comments and blank space, so that a comment edit keeps a traffic record."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def kernel_source_hash(kernel: str, read=None) -> str:
+    """Hash of the code a kernel is built from (comments ignored); a traffic record is used only while
+    it matches. ``read(name)`` returns a source file's text (default: the files in the tree)."""
     h = hashlib.sha256()
     for name in KERNEL_SOURCES[kernel]:
-        with open(os.path.join(ROOT, "paper_1710_10789_amd", "csrc", name), "rb") as f:
-            h.update(name.encode())
-            h.update(f.read())
+        if read is None:
+            with open(os.path.join(ROOT, "paper_1710_10789_amd", "csrc", name), encoding="utf-8") as f:
+                text = f.read()
+        else:
+            text = read(name)
+        h.update(name.encode())
+        h.update(_code_only(text).encode())
     return h.hexdigest()[:16]
 
 

@@ -13,7 +13,7 @@
 // weights w_l and their energy derivatives taken from the five energy cases of Sec. II.C, evaluated
 // on the four corner energies of each tetrahedron sorted ascending (Sec. II.C).
 //
-// Readings of points the paper leaves open (all listed in the design notes):
+// Readings of points the paper leaves open:
 //  R1 cube corner label L = 1 + o1 + 2*o2 + 4*o3, o_a in {0,1} the offset along grid axis a
 //     (axis 1 is the slowest array index, k = (i1*n2 + i2)*n3 + i3); Table I is used as printed.
 //  R2 periodic grid of n1*n2*n3 cubes, so V_T/V_G = 1/(6*n1*n2*n3).

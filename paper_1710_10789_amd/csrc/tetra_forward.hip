@@ -4,7 +4,7 @@
 // (eq. tetmethoorbitalresolved, Guterding & Jeschke, arXiv:1710.10789, Sec. II.C), with the
 // tetrahedra of Table I.
 //
-// Work decomposition (differs from the paper's Sec. III.B on purpose; see the design notes):
+// Work decomposition (differs from the paper's Sec. III.B on purpose):
 //  * one workgroup per (tile of TX x TY x TZ cubes, band); one lane per cube, looping over the six
 //    tetrahedra of Table I. Cube corner indices are computed from the lane's coordinates (no index
 //    table), and the (TX+1)(TY+1)(TZ+1) grid points of the tile are staged once in LDS (energies and
