@@ -141,3 +141,23 @@ def test_batched_per_item_tile_shapes(torch_dev, oracle_lib):
     for o, (eps, w, grid, e0, de, ne) in zip(outs, host):
         ref, _ = oracle_lib.dos(eps, w, grid, e0, de, ne)
         assert _err(o.cpu().numpy().astype(np.float64), ref) <= 1e-5
+
+
+def test_batched_sixteen_orbitals_fp16(torch_dev, oracle_lib):
+    """The largest orbital count through the persistent launch, with FP16 weights and per-item tiles."""
+    torch, dev = torch_dev
+    import paper_1710_10789_amd as tetra
+
+    probs, refs = [], []
+    for seed, grid, ne in ((21, (8, 9, 10), 700), (22, (12, 5, 16), 1300), (23, (3, 4, 33), 256)):
+        eps, w = synth.band_structure(16, seed, grid)
+        e0, de = synth.energy_grid(eps, ne)
+        w16, scale = tetra.half_weights(torch.from_numpy(w))
+        deq = (w16.float() * scale[:, None, None]).numpy()
+        probs.append((torch.from_numpy(eps).to(dev), w16.to(dev), grid, e0, de, ne, scale.to(dev)))
+        refs.append(oracle_lib.dos(eps, deq, grid, e0, de, ne)[0])
+    print(f"[case] batched norb 16 fp16, {len(probs)} items", flush=True)
+    outs = tetra.dos_batched(probs, tiles=[5, 2, 0])
+    torch.cuda.synchronize()
+    for o, ref in zip(outs, refs):
+        assert _err(o.cpu().numpy().astype(np.float64), ref) <= 1e-5
