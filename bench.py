@@ -42,6 +42,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = {
     "dos_forward_kernel": ("tetra_forward.hip", "tetra_device.h", "tetra_internal.h"),
     "dos_backward_kernel": ("tetra_backward.hip", "tetra_device.h", "tetra_internal.h"),
+    "nos_kernel": ("tetra_nos.hip", "tetra_nos_device.h", "tetra_device.h", "tetra_internal.h"),
 }
 
 
@@ -104,6 +105,43 @@ def algorithmic_flops(uwin, norb):
     orbital sums s_c and dL/db (16*norb), 4 weights (24), 16 cubic partials (96), a 16-term
     contraction (32)."""
     return uwin * (8 * norb + 24), uwin * (16 * norb + 152)
+
+
+def count_step_updates(eps, grid, e0, de, ne, joff=0.0):
+    """Number of (tetrahedron, band, grid index) triples at which a tetrahedron-band's number of states
+    changes on the grid E_j = e0 + (j + joff) de, j = 0..ne-1: from the first E_j > E1 to the first
+    E_j >= E4, clipped to the grid (everything below the grid counts once, at j = 0)."""
+    n1, n2, n3 = grid
+    nb = eps.shape[0]
+    e = eps.reshape(nb, n1, n2, n3).astype(np.float64)
+    origin = e0 + joff * de
+    total = 0
+    for tet in table1_offsets():
+        lo = None
+        hi = None
+        for o in tet:
+            c = np.roll(e, shift=(-o[0], -o[1], -o[2]), axis=(1, 2, 3))
+            lo = c if lo is None else np.minimum(lo, c)
+            hi = c if hi is None else np.maximum(hi, c)
+        ok = np.isfinite(lo) & np.isfinite(hi)
+        lo, hi = lo[ok], hi[ok]
+        # ja: first j with E_j > lo; js: first j with E_j >= hi (clipped to [-1, ne] before refining)
+        ja = np.clip(np.floor((lo - origin) / de), -1, ne).astype(np.int64)
+        ja += (origin + ja * de <= lo)
+        ja -= (origin + (ja - 1) * de > lo)
+        js = np.clip(np.ceil((hi - origin) / de), -1, ne).astype(np.int64)
+        js += (origin + js * de < hi)
+        js -= (origin + (js - 1) * de >= hi)
+        js0 = np.maximum(js, 0)
+        ja0 = np.minimum(np.maximum(ja, 0), js0)
+        total += int(np.maximum(np.minimum(js0, ne - 1) - ja0 + 1, 0).sum())
+    return total
+
+
+def nos_flops(ustep, norb):
+    """Per number-of-states increment: 4 corners x norb FMAs, 4 corner quartics (4 x 4 FMAs) and 4
+    differences: 8*norb + 36 flops."""
+    return ustep * (8 * norb + 36)
 
 
 def algorithmic_bytes(nk, nb, norb, ne):
@@ -194,14 +232,20 @@ def summarize_profiles(kt_dir, fetch_dir=None, write_dir=None, copy_fetch_dir=No
                 continue
             rd, wt = fe[k] * 1024 * f_fetch, wr[k] * 1024 * f_write
             lines.append(f"| `{k[:90]}` | {fe[k]:.0f} | {wr[k]:.0f} | {rd / 1e6:.2f} | {wt / 1e6:.2f} |")
-            for short in ("dos_forward_kernel", "dos_backward_kernel"):
+            for short in ("dos_forward_kernel", "dos_backward_kernel", "nos_kernel"):
                 if short in k:
                     sha = (source_shas or {}).get(short) or kernel_source_hash(short)
                     traffic[short] = {"source_sha": sha, "bytes_per_launch": rd + wt,
                                       "read_bytes": rd, "write_bytes": wt}
     if out_json and traffic:
+        try:  # keep the records of kernels this run did not profile
+            with open(out_json) as f:
+                merged = json.load(f)
+        except (OSError, ValueError):
+            merged = {}
+        merged.update(traffic)
         with open(out_json, "w") as f:
-            json.dump(traffic, f, indent=1)
+            json.dump(merged, f, indent=1)
     text = "\n".join(lines)
     if command:
         text = f"Command: `{command}`\n\n" + text
@@ -326,6 +370,87 @@ def bench_paper_shape(args, torch, tetra, dev):
     }), flush=True)
 
 
+def bench_nos(args, torch, tetra, dev):
+    """Number of states and bin-averaged DOS at the headline shape (64^3 x 8 bands x 8 orbitals x 1000
+    energies): one pass of each, inputs resident; tile shape by a short sweep outside the timed
+    region. The FP64 oracle (dense in energy) is timed on the whole workload."""
+    c = synth.config(WORKLOAD)
+    grid, norb, ne = c["grid"], c["norb"], c["ne"]
+    eps_np, w_np = synth.band_structure(norb, c["seed"], grid)
+    e0, de = synth.energy_grid(eps_np, ne)
+    nb, nk = eps_np.shape
+    dense = 6 * nk * nb * ne
+    u_nos = count_step_updates(eps_np, grid, e0, de, ne)
+    u_bin = count_step_updates(eps_np, grid, e0, de, ne + 1, joff=-0.5)
+    eps = torch.from_numpy(eps_np).to(dev)
+    w = torch.from_numpy(w_np).to(dev)
+    out_n = torch.empty((ne, norb), device=dev)
+    out_b = torch.empty((ne, norb), device=dev)
+    if args.tiles:  # every launch of the run with the given shape (for profiles)
+        tile, sweep = int(args.tiles.split(",")[0]), None
+    else:
+        sweep = {t: _time_events(torch, lambda t=t: tetra.dos_binned(eps, w, grid, e0, de, ne, out=out_b, tile=t),
+                                 3, 1) for t in range(len(tetra.TILE_SHAPES))}
+        tile = min(sweep, key=sweep.get)
+    stream = torch.cuda.current_stream(dev)
+    runs = {"nos": lambda: tetra.nos_forward(eps, w, grid, e0, de, ne, out=out_n, tile=tile),
+            "binned": lambda: tetra.dos_binned(eps, w, grid, e0, de, ne, out=out_b, tile=tile)}
+    ms = {}
+    for k, f in runs.items():
+        for _ in range(args.warmup):
+            f()
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        for e in ev:
+            e[0].record(stream)
+            f()
+            e[1].record(stream)
+        torch.cuda.synchronize()
+        ms[k] = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    flops = nos_flops(u_bin, norb)
+    achieved = flops / (ms["binned"] * 1e-3) / 1e12
+    rec = {
+        "metric": "tetra-band-energy updates/s, number of states at 64^3 k, 8 bands, 1000 E",
+        "value": dense / (ms["nos"] * 1e-3),
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms["nos"],
+        "higher_is_better": True,
+        "dtype": "f32",
+        "data": "synthetic (seeded random 8-orbital tight-binding model; eigh on the host, untimed)",
+        "config": {"workload": f"{WORKLOAD}: 64^3 periodic k-grid, 8 bands x 8 orbitals, 1000 energies, FP32 SoA",
+                   "dense_updates_per_pass": dense, "step_updates_nos": u_nos, "step_updates_binned": u_bin,
+                   "tile": list(tetra.TILE_SHAPES[tile])},
+        "ms": ms,
+        "binned_updates_per_s": dense / (ms["binned"] * 1e-3),
+        "roofline": {"bound": "alu", "kernel": "nos_kernel (bin averages; events include the zero fill)",
+                     "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": load_traffic("nos_kernel"),
+                     "algorithmic_flops_per_launch": flops, "avg_launch_ms": ms["binned"]},
+        "tile_sweep_ms": sweep,
+        "kernel_source_sha": {"nos_kernel": kernel_source_hash("nos_kernel")},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+
+        oracle.build()
+        cores = len(os.sched_getaffinity(0))
+        print(f"[nos] FP64 oracle on {cores} threads", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        ref = oracle.nos(eps_np, w_np, grid, e0, de, ne, nthreads=cores)
+        t_or = time.perf_counter() - t0
+        runs["nos"]()
+        torch.cuda.synchronize()
+        got = out_n.cpu().numpy().astype(np.float64)
+        rec["cpu_baseline"] = {"value": dense / t_or, "unit": "updates/s", "cores": cores, "kind": "oracle",
+                               "sample": f"the whole workload, one number-of-states pass ({ne} energies), FP64 "
+                                         f"({t_or:.1f} s)"}
+        rec["nos_err_vs_oracle"] = float(np.abs(got - ref).max() / np.abs(ref).max())
+    print(json.dumps(rec), flush=True)
+
+
 def bench_batched(args, torch, tetra, dev):
     """32 independently seeded 8-orbital models, cubic grids from {24,32,48,64,96}^3 and 256..2048
     energies, through one persistent launch captured in a HIP graph, tile shapes per problem from the
@@ -404,10 +529,11 @@ def main():
     ap.add_argument("--mode", choices=["fwdbwd", "fwd"], default="fwdbwd")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tiles", help="forward,backward tile shape ids (skips the autotuner)")
-    ap.add_argument("--workload", choices=["headline", "precision", "batched", "paper"], default="headline",
+    ap.add_argument("--workload", choices=["headline", "precision", "batched", "paper", "nos"], default="headline",
                     help="headline: 64^3 x 8 x 8 x 1000 fwd+bwd (the metric); precision: 128^3 x 16 x 16 x 2000 "
                          "with FP16 weights and exact accumulation; batched: 32 models, one persistent launch; "
-                         "paper: the paper's 60 x 60 x 10 x 8 x 1024 forward, for context")
+                         "paper: the paper's 60 x 60 x 10 x 8 x 1024 forward, for context; nos: number of states "
+                         "and bin-averaged DOS at the headline shape")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device-to-device copy of 256 MiB (5 times) to scale HBM byte counters")
     args = ap.parse_args()
@@ -437,6 +563,8 @@ def main():
         return bench_batched(args, torch, tetra, dev)
     if args.workload == "paper":
         return bench_paper_shape(args, torch, tetra, dev)
+    if args.workload == "nos":
+        return bench_nos(args, torch, tetra, dev)
     c = synth.config(WORKLOAD)
     grid, norb, ne = c["grid"], c["norb"], c["ne"]
     eps_np, w_np = synth.band_structure(norb, c["seed"], grid)

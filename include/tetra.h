@@ -122,6 +122,34 @@ tetra_status tetra_dos_backward(const tetra_desc* d, const float* eps, const voi
                                 const float* w_scale, const float* grad_dos, float* grad_eps,
                                 float* grad_w, unsigned flags, void* stream);
 
+/*
+ * Orbital-resolved number of states (eq. BZintegral with X = b of eq. matrixelements and the step
+ * occupation at E_j; the integrated corner weights w_l of Sec. II.C):
+ *
+ *   nos[j][m] = sum over cubes, tetrahedra of Table I, bands n and corners l of b[n][m][k_l] w_{n,l}(E_j)
+ *
+ * with w_l = 0 for E_j <= E1 and w_l = V_T/(4 V_G) for E_j >= E4, so nos[j][m] counts the states of
+ * orbital m up to E_j per k-point (unit cell). Arguments as for tetra_dos_forward; nos is device
+ * float [ne][norb], overwritten. flags: TETRA_TILE(shape) or 0 (TETRA_KAHAN and TETRA_DETERMINISTIC
+ * give TETRA_ERR_UNSUPPORTED). Allocates nothing.
+ */
+tetra_status tetra_nos_forward(const tetra_desc* d, const float* eps, const void* w, int wtype,
+                               const float* w_scale, float* nos, unsigned flags, void* stream);
+
+/*
+ * Bin-averaged orbital-resolved DOS: the increase of the number of states across the bin of width de
+ * centred on each grid energy,
+ *
+ *   dos[j][m] = (N_m(E_j + de/2) - N_m(E_j - de/2)) / de,
+ *
+ * with N_m as in tetra_nos_forward. Each tetrahedron-band contributes the exact integral of its
+ * piecewise-polynomial corner DOS over the bin, so sum_j dos[j][m] de equals
+ * N_m(e0 + (ne - 1/2) de) - N_m(e0 - de/2) (no sampling of peaks narrower than de). Arguments and
+ * flags as for tetra_nos_forward; dos is device float [ne][norb], overwritten. Allocates nothing.
+ */
+tetra_status tetra_dos_binned(const tetra_desc* d, const float* eps, const void* w, int wtype,
+                              const float* w_scale, float* dos, unsigned flags, void* stream);
+
 /* One problem of a batch: its descriptor and device buffers (same meaning as tetra_dos_forward). */
 typedef struct {
   tetra_desc d;

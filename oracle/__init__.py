@@ -135,6 +135,14 @@ def nos(eps, w, grid, e0, de, ne, nthreads=None):
     return out
 
 
+def dos_binned(eps, w, grid, e0, de, ne, nthreads=None):
+    """FP64 bin-averaged DOS ``[ne, norb]``: (N(E_j + de/2) - N(E_j - de/2)) / de with N the number of
+    states above (Sec. II: the DOS is the energy derivative of the orbital-resolved particle number),
+    from N on the ne + 1 bin edges e0 - de/2 + i de (exact in FP64 for FP32 e0, de)."""
+    edges = nos(eps, w, grid, float(e0) - 0.5 * float(de), de, int(ne) + 1, nthreads)
+    return np.diff(edges, axis=0) / float(de)
+
+
 def dos_backward(eps, w, grid, e0, de, G, nthreads=None):
     """``(dL/deps [nb, nk], dL/dw [nb, norb, nk])`` in FP64 for ``G = dL/dDOS [ne, norb]``."""
     eps, w, n1, n2, n3, nb, norb = _grid_args(eps, w, grid)

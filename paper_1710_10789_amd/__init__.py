@@ -23,6 +23,8 @@ __all__ = [
     "make_desc",
     "dos_forward",
     "dos_backward",
+    "nos_forward",
+    "dos_binned",
     "dos",
     "dos_batched",
     "batched_workspace_bytes",
@@ -102,6 +104,10 @@ def lib():
         p, i, u = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint
         L.tetra_dos_forward.argtypes = [ctypes.POINTER(TetraDesc), p, p, i, p, p, u, p]
         L.tetra_dos_forward.restype = i
+        L.tetra_nos_forward.argtypes = [ctypes.POINTER(TetraDesc), p, p, i, p, p, u, p]
+        L.tetra_nos_forward.restype = i
+        L.tetra_dos_binned.argtypes = [ctypes.POINTER(TetraDesc), p, p, i, p, p, u, p]
+        L.tetra_dos_binned.restype = i
         L.tetra_dos_backward.argtypes = [ctypes.POINTER(TetraDesc), p, p, i, p, p, p, p, u, p]
         L.tetra_dos_backward.restype = i
         L.tetra_dos_batched_workspace.argtypes = [ctypes.POINTER(TetraItem), i, i, u]
@@ -170,6 +176,49 @@ def _shapes(eps, w, grid):
         raise ValueError("eps must be [nb, nk] and w [nb, norb, nk]")
     nb, norb = w.shape[0], w.shape[1]
     return nk, nb, norb
+
+
+def _weights_type(torch, w, w_scale, nb, dev):
+    wtype = TETRA_W_F16 if w.dtype == torch.float16 else TETRA_W_F32
+    if wtype == TETRA_W_F16:
+        if w_scale is None:
+            raise ValueError("float16 weights need w_scale")
+        _require(w_scale, "w_scale", (nb,), (torch.float32,), dev)
+    elif w_scale is not None:
+        raise ValueError("w_scale is only used with float16 weights")
+    return wtype
+
+
+def _integrated(func, eps, w, grid, e0, de, ne, w_scale, out, tile):
+    torch = _torch()
+    nk, nb, norb = _shapes(eps, w, grid)
+    dev = eps.device
+    _require(eps, "eps", (nb, nk), (torch.float32,), dev)
+    _require(w, "w", (nb, norb, nk), (torch.float32, torch.float16), dev)
+    wtype = _weights_type(torch, w, w_scale, nb, dev)
+    if out is None:
+        out = torch.empty((int(ne), norb), dtype=torch.float32, device=dev)
+    _require(out, "out", (int(ne), norb), (torch.float32,), dev)
+    d = make_desc(grid, nb, norb, e0, de, ne)
+    st = getattr(lib(), func)(
+        ctypes.byref(d), eps.data_ptr(), w.data_ptr(), wtype,
+        w_scale.data_ptr() if w_scale is not None else None, out.data_ptr(), _tile_flag(tile),
+        _stream_handle(dev))
+    _check(func, st)
+    return out
+
+
+def nos_forward(eps, w, grid, e0, de, ne, *, w_scale=None, out=None, tile=None):
+    """Orbital-resolved number of states ``[ne, norb]`` (FP32) at E_j = e0 + j*de: the states of each
+    orbital up to E_j per k-point. Arguments as for ``dos_forward``."""
+    return _integrated("tetra_nos_forward", eps, w, grid, e0, de, ne, w_scale, out, tile)
+
+
+def dos_binned(eps, w, grid, e0, de, ne, *, w_scale=None, out=None, tile=None):
+    """Bin-averaged orbital-resolved DOS ``[ne, norb]``: (N(E_j + de/2) - N(E_j - de/2)) / de, the
+    number of states gained across the bin of width de centred on E_j, divided by de. Arguments as
+    for ``dos_forward``."""
+    return _integrated("tetra_dos_binned", eps, w, grid, e0, de, ne, w_scale, out, tile)
 
 
 def dos_forward(eps, w, grid, e0, de, ne, *, w_scale=None, kahan=False, deterministic=False, out=None, tile=None):

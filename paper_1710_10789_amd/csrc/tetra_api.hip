@@ -112,6 +112,34 @@ tetra_status tetra_dos_backward(const tetra_desc* d, const float* eps, const voi
                                     grad_w, shape, (hipStream_t)stream));
 }
 
+namespace {
+
+tetra_status nos_entry(const tetra_desc* d, const float* eps, const void* w, int wtype, const float* w_scale,
+                       float* out, unsigned flags, void* stream, bool binned) {
+  tetra_status st = check_desc(d);
+  if (st != TETRA_OK) return st;
+  if (!eps || !w || !out) return TETRA_ERR_ARG;
+  if ((st = check_weights(wtype, w_scale)) != TETRA_OK) return st;
+  if (flags & ~(unsigned)(TETRA_KAHAN | TETRA_DETERMINISTIC | TETRA_TILE_MASK)) return TETRA_ERR_ARG;
+  const int shape = (int)((flags & TETRA_TILE_MASK) >> 8);
+  if (shape >= tetra::kTileShapes) return TETRA_ERR_ARG;
+  if (flags & (TETRA_KAHAN | TETRA_DETERMINISTIC)) return TETRA_ERR_UNSUPPORTED;
+  return hip_status(tetra::nos(*d, eps, w, wtype == TETRA_W_F16 ? w_scale : nullptr, out, binned, shape,
+                               (hipStream_t)stream));
+}
+
+}  // namespace
+
+tetra_status tetra_nos_forward(const tetra_desc* d, const float* eps, const void* w, int wtype,
+                               const float* w_scale, float* nos, unsigned flags, void* stream) {
+  return nos_entry(d, eps, w, wtype, w_scale, nos, flags, stream, false);
+}
+
+tetra_status tetra_dos_binned(const tetra_desc* d, const float* eps, const void* w, int wtype,
+                              const float* w_scale, float* dos, unsigned flags, void* stream) {
+  return nos_entry(d, eps, w, wtype, w_scale, dos, flags, stream, true);
+}
+
 size_t tetra_dos_batched_workspace(const tetra_item* items, int n, int wtype, unsigned flags) {
   if (!items || n < 1 || (wtype != TETRA_W_F32 && wtype != TETRA_W_F16) || flags != 0) return 0;
   for (int i = 0; i < n; ++i)

@@ -35,6 +35,9 @@ hipError_t forward(const tetra_desc& d, const float* eps, const void* w, const f
 size_t batched_launches(const tetra_item* items, int n);
 hipError_t batched(const tetra_item* items, const int* shapes, int n, bool half, void* workspace, hipStream_t s);
 inline size_t forward_exact_scratch_bytes(const tetra_desc& d) { return 256 + 8 * (size_t)d.ne * d.norb; }
+// Number of states (binned = false) or bin-averaged DOS (binned = true) into out[ne][norb].
+hipError_t nos(const tetra_desc& d, const float* eps, const void* w, const float* w_scale, float* out, bool binned,
+               int shape, hipStream_t s);
 hipError_t backward(const tetra_desc& d, const float* eps, const void* w, const float* w_scale, const float* G,
                     float* grad_eps, float* grad_w, int shape, hipStream_t s);
 

@@ -1,0 +1,372 @@
+// Number-of-states kernel: orbital-resolved number of states and bin-averaged DOS on gfx950.
+//
+// N[j][m] = sum over the tetrahedra of Table I, bands n and corners l of b[n][m][k_l] w_{n,l}(E_j):
+// eq. (BZintegral) with X = b of eq. (matrixelements) and the step occupation at E_j, summed by the
+// tetrahedron method (eqs. tetmethod, tetracontrib) with the integrated corner weights w_l of the five
+// energy cases of Sec. II.C (arXiv:1710.10789).
+//
+// A tetrahedron-band's w_l(E) is zero up to E1, a polynomial on (E1, E4) and V_T/(4 V_G) from E4 on,
+// so over the grid it is described by its increments w_l(E_j) - w_l(E_{j-1}), non-zero only from the
+// first E_j > E1 to the first E_j >= E4. The kernel adds those increments (contracted with the corner
+// weights b) into a histogram, and a scan over j afterwards sums them to N: the work follows the
+// tetrahedron's window, not the energies above it. The increments on the grid of midpoints
+// E_j -+ de/2, divided by de, are the bin averages (N(E_j + de/2) - N(E_j - de/2)) / de of the DOS,
+// whose sum over the bins telescopes to the difference of N at the two outer edges.
+//
+// Work decomposition and accumulation as in the forward DOS kernel: one workgroup per (tile of cubes,
+// band), one lane per cube looping over the six tetrahedra, the tile's grid points staged in LDS, a
+// five-comparator corner sort, and an exact fixed-point LDS histogram over the tile-band's range of
+// grid indices (two orbitals per 64-bit word when the weights are non-negative; every increment is
+// then non-negative too, w_l being non-decreasing in E). A bin's sum over the tile's tetrahedra is at
+// most 4 V bmax per tetrahedron (the increments of one corner add up to V), which fixes the scale.
+
+#include "tetra_internal.h"
+#include "tetra_nos_device.h"
+
+namespace tetra {
+
+namespace {
+
+constexpr int NT = kTileCubes;
+constexpr int NPMAX = kTilePointsMax;
+constexpr int HCAP = 2048;  // LDS histogram capacity in 64-bit words
+constexpr int NXCD = 8;
+
+struct NosArgs {
+  const float* eps;
+  const void* w;         // float or _Float16 [nb][norb][nk]
+  const float* w_scale;  // per-band scale of _Float16 weights
+  float* out;            // [nout][norb]
+  int n1, n2, n3;
+  int ng;      // grid indices j = 0..ng-1 at E_j = e0 + (j + joff) de
+  int shift;   // grid index j is written to output row j - shift (rows below 0 are dropped)
+  int nout;    // output rows
+  float e0, de, inv_de, joff, V;
+  double out_scale;  // applied to every flushed sum (1, or 1/de for bin averages)
+  int TX, TY, TZ;
+  int t1, t2, t3;
+  int ntiles, nunits, per_xcd;
+};
+
+__device__ __forceinline__ int wrap(int v, int n) {
+  if (v >= n) v -= n;
+  if (v >= n) v %= n;
+  return v;
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+
+template <int NORB, typename WT>
+__global__ __launch_bounds__(NT) void nos_kernel(NosArgs a) {
+  constexpr int NPAIR = (NORB + 1) / 2;
+  constexpr int RSP = (HCAP / NPAIR - 1) | 1, RSW = (HCAP / NORB - 1) | 1;
+  __shared__ float s_eps[NPMAX];
+  __shared__ float s_w[NPMAX * NORB];
+  __shared__ unsigned long long s_hist[HCAP];
+  __shared__ float s_red[4 * (NT / 64)];
+
+  const int b = blockIdx.x;
+  const int unit = (b % NXCD) * a.per_xcd + b / NXCD;  // XCD-aware: contiguous tiles per XCD
+  if (unit >= a.nunits) return;
+  const int TX = a.TX, TY = a.TY, TZ = a.TZ;
+  const int PY = TY + 1, PZ = TZ + 1;
+  const int NP = (TX + 1) * PY * PZ;
+  const int band = unit / a.ntiles;
+  const int tile = unit - band * a.ntiles;
+  const int tz = tile % a.t3;
+  const int ty = (tile / a.t3) % a.t2;
+  const int tx = tile / (a.t3 * a.t2);
+  const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+  const int tid = threadIdx.x;
+  const int64_t nk = (int64_t)a.n1 * a.n2 * a.n3;
+  const float* eps_n = a.eps + (int64_t)band * nk;
+  const WT* w_n = static_cast<const WT*>(a.w) + (int64_t)band * NORB * nk;
+  const float wscale = a.w_scale ? a.w_scale[band] : 1.0f;
+
+  float lmin = __builtin_huge_valf(), lmax = -__builtin_huge_valf(), lbmax = 0.0f, lbmin = 0.0f;
+  for (int p = tid; p < NP; p += NT) {
+    const int pz = p % PZ, py = (p / PZ) % PY, px = p / (PZ * PY);
+    const int64_t k = ((int64_t)wrap(x0 + px, a.n1) * a.n2 + wrap(y0 + py, a.n2)) * a.n3 + wrap(z0 + pz, a.n3);
+    const float e = eps_n[k];
+    s_eps[p] = e;
+    if (__builtin_isfinite(e)) {
+      lmin = fminf(lmin, e);
+      lmax = fmaxf(lmax, e);
+    }
+#pragma unroll
+    for (int m = 0; m < NORB; ++m) {
+      const float v = (float)w_n[(int64_t)m * nk + k] * wscale;
+      s_w[p * NORB + m] = v;
+      lbmax = fmaxf(lbmax, fabsf(v));
+      lbmin = fminf(lbmin, v);
+    }
+  }
+  lmin = wave_min(lmin);
+  lmax = wave_max(lmax);
+  lbmax = wave_max(lbmax);
+  lbmin = wave_min(lbmin);
+  if ((tid & 63) == 0) {
+    s_red[tid >> 6] = lmin;
+    s_red[(NT / 64) + (tid >> 6)] = lmax;
+    s_red[2 * (NT / 64) + (tid >> 6)] = lbmax;
+    s_red[3 * (NT / 64) + (tid >> 6)] = lbmin;
+  }
+  __syncthreads();
+  float emin = s_red[0], emax = s_red[NT / 64], bmax = s_red[2 * (NT / 64)], bmin = s_red[3 * (NT / 64)];
+#pragma unroll
+  for (int i = 1; i < NT / 64; ++i) {
+    emin = fminf(emin, s_red[i]);
+    emax = fmaxf(emax, s_red[NT / 64 + i]);
+    bmax = fmaxf(bmax, s_red[2 * (NT / 64) + i]);
+    bmin = fminf(bmin, s_red[3 * (NT / 64) + i]);
+  }
+  if (!(emin <= emax) || !(bmax > 0.0f)) return;  // nothing to add (uniform across the block)
+  // Grid indices this tile-band can touch: from the first E_j above its lowest energy to the first
+  // E_j at or above its highest, one index of margin for the FP32 estimates.
+  const float big = 3.0e7f;
+  const float tlo = fminf(fmaxf((emin - a.e0) * a.inv_de - a.joff, -2.0f), big);
+  const float thi = fminf(fmaxf((emax - a.e0) * a.inv_de - a.joff, -2.0f), big);
+  // (a tile-band entirely below the grid puts all its states at index 0)
+  const int J0 = max((int)floorf(tlo) - 1, 0);
+  const int J1 = min(max((int)ceilf(thi) + 1, 0), a.ng - 1);
+  if (J0 > J1) return;  // the tile-band lies above the grid
+
+  const int cz = tid % TZ, cy = (tid / TZ) % TY, cx = tid / (TZ * TY);
+  const bool valid = (x0 + cx < a.n1) && (y0 + cy < a.n2) && (z0 + cz < a.n3);
+  const int pbase = (cx * PY + cy) * PZ + cz;
+  auto point_offset = [PY, PZ](int s) { return (s & 1) * (PY * PZ) + ((s >> 1) & 1) * PZ + (s >> 2); };
+
+  const bool packed = bmin >= 0.0f;  // uniform across the block
+  const int rows = packed ? NPAIR : NORB;
+  const int RS = packed ? RSP : RSW;
+  const int span = J1 - J0 + 1;
+  const int cpl = span <= (RS >> 3) ? 3 : span <= (RS >> 2) ? 2 : span <= (RS >> 1) ? 1 : 0;  // log2 of copies
+  const int CP = 1 << cpl;
+  const int LC = RS >> cpl;
+  // Bound on any bin: 4 V bmax for each of the tile's 6 NT tetrahedra.
+  const float B = 24.0f * (float)NT * a.V * bmax;
+  int bexp;
+  frexpf(fminf(B, 3.0e38f), &bexp);
+  const int sexp = min((packed ? 30 : 62) - bexp, 126);
+  const float S = ldexpf(1.0f, sexp);
+  const double inv_S = ldexp(1.0, -sexp) * a.out_scale;
+  const float V = a.V;
+  // Fold the power-of-two scale into the staged weights (exact).
+  for (int q = tid; q < NP * NORB; q += NT) s_w[q] *= S;
+  __syncthreads();
+
+  for (int c0 = J0; c0 <= J1; c0 += LC) {
+    const int c1 = min(c0 + LC - 1, J1);
+    const int L = c1 - c0 + 1;
+    const int LW = L << cpl;
+    for (int q = tid; q < rows * LW; q += NT) {
+      const int r = q / LW;
+      s_hist[r * RS + (q - r * LW)] = 0ull;
+    }
+    __syncthreads();
+    if (valid) {
+#pragma unroll 1
+      for (int t = 0; t < 6; ++t) {
+        const uint32_t slots = tet_slots(t);
+        float e[4];
+        int pt[4];
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+          pt[l] = pbase + point_offset((slots >> (4 * l)) & 7);
+          e[l] = s_eps[pt[l]];
+        }
+        if (!finite4(e[0], e[1], e[2], e[3])) continue;
+        sort4(e, pt);
+        TetSetup cs = tet_setup(e, a.e0, V);
+        shift_frames(cs, a.joff * a.de);
+        int ja, js;
+        step_window(cs, e[0], e[3], a.e0, a.joff, a.de, a.inv_de, ja, js);
+        const int js0 = max(js, 0);                 // the step's grid index (everything below the grid at 0)
+        const int ja0 = min(max(ja, 0), js0);        // first grid index with an increment
+        const int jend = min(js0, c1);
+        if (jend < c0) continue;                     // no increment in this pass
+        // Before this pass: start one index early to know w there, without adding its increment.
+        const int jstart = ja0 < c0 ? c0 - 1 : ja0;
+        int jA, jB;
+        case_split(cs, a.de, a.inv_de, jstart, min(jend, js0 - 1), jA, jB);
+        float bb[4][NORB];
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+#pragma unroll
+          for (int m = 0; m < NORB; ++m) bb[l][m] = s_w[pt[l] * NORB + m];
+        }
+        auto deposit = [&](int j, const float g[4]) {
+          unsigned long long* h = &s_hist[((j - c0) << cpl) + (tid & (CP - 1))];
+          if (packed) {
+#pragma unroll
+            for (int pr = 0; pr < NPAIR; ++pr) {
+              const int m0 = 2 * pr, m1 = 2 * pr + 1;
+              float v0 = __builtin_fmaf(g[0], bb[0][m0], 0.5f);
+              v0 = __builtin_fmaf(g[1], bb[1][m0], v0);
+              v0 = __builtin_fmaf(g[2], bb[2][m0], v0);
+              v0 = __builtin_fmaf(g[3], bb[3][m0], v0);
+              unsigned long long word = (unsigned long long)(unsigned)v0;
+              if (m1 < NORB) {
+                float v1 = __builtin_fmaf(g[0], bb[0][m1], 0.5f);
+                v1 = __builtin_fmaf(g[1], bb[1][m1], v1);
+                v1 = __builtin_fmaf(g[2], bb[2][m1], v1);
+                v1 = __builtin_fmaf(g[3], bb[3][m1], v1);
+                word |= (unsigned long long)(unsigned)v1 << 32;
+              }
+              atomicAdd(&h[pr * RSP], word);
+            }
+          } else {
+#pragma unroll
+            for (int m = 0; m < NORB; ++m) {
+              const float v = g[0] * bb[0][m] + g[1] * bb[1][m] + g[2] * bb[2][m] + g[3] * bb[3][m];
+              atomicAdd(&h[m * RSW], (unsigned long long)__float2ll_rn(v));
+            }
+          }
+        };
+        float coef[4][5];
+        if (jB > jA) corner_nos_B_coeffs(cs, V, coef);
+        float prev[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int j = jstart; j <= jend; ++j) {
+          float cur[4];
+          if (j >= js0) {
+#pragma unroll
+            for (int l = 0; l < 4; ++l) cur[l] = V;
+          } else if (j <= jA) {
+            corner_nos_A(cs, local_x(cs, j, a.de), cur);
+          } else if (j <= jB) {
+            corner_nos_B_poly(coef, local_z(cs, j, a.de), cur);
+          } else {
+            corner_nos_C(cs, V, local_y(cs, j, a.de), cur);
+          }
+          if (j >= c0) {
+            float inc[4];
+            // w_l is non-decreasing in E; a negative difference is rounding
+#pragma unroll
+            for (int l = 0; l < 4; ++l) inc[l] = fmaxf(cur[l] - prev[l], 0.0f);
+            deposit(j, inc);
+          }
+#pragma unroll
+          for (int l = 0; l < 4; ++l) prev[l] = cur[l];
+        }
+      }
+    }
+    __syncthreads();
+    for (int q = tid; q < L * NORB; q += NT) {
+      const int r = q / NORB, m = q - r * NORB;
+      const int orow = c0 + r - a.shift;
+      if (orow < 0 || orow >= a.nout) continue;
+      const int row = packed ? (m >> 1) : m;
+      const unsigned long long* hw = &s_hist[row * RS + (r << cpl)];
+      double sum = 0.0;
+      for (int c = 0; c < CP; ++c) {
+        const unsigned long long w = hw[c];
+        sum += packed ? (double)(unsigned)((m & 1) ? (w >> 32) : (w & 0xffffffffull)) : (double)(long long)w;
+      }
+      if (sum != 0.0) unsafeAtomicAdd(&a.out[(int64_t)orow * NORB + m], (float)(sum * inv_S));
+    }
+    __syncthreads();
+  }
+}
+
+// In-place running sum over rows of p[n][norb], one workgroup per column, accumulated in FP64.
+__global__ __launch_bounds__(256) void column_scan_kernel(float* p, int n, int norb) {
+  __shared__ double s_part[256];
+  const int m = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int per = (n + 255) / 256;
+  const int r0 = min(tid * per, n), r1 = min(r0 + per, n);
+  double acc = 0.0;
+  for (int r = r0; r < r1; ++r) acc += (double)p[(int64_t)r * norb + m];
+  s_part[tid] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    double run = 0.0;
+    for (int i = 0; i < 256; ++i) {
+      const double v = s_part[i];
+      s_part[i] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  double run = s_part[tid];
+  for (int r = r0; r < r1; ++r) {
+    run += (double)p[(int64_t)r * norb + m];
+    p[(int64_t)r * norb + m] = (float)run;
+  }
+}
+
+template <int NORB>
+hipError_t launch_nos(const NosArgs& a, int grid, hipStream_t s) {
+  if (a.w_scale)
+    hipLaunchKernelGGL((nos_kernel<NORB, _Float16>), dim3(grid), dim3(NT), 0, s, a);
+  else
+    hipLaunchKernelGGL((nos_kernel<NORB, float>), dim3(grid), dim3(NT), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t nos(const tetra_desc& d, const float* eps, const void* w, const float* w_scale, float* out, bool binned,
+               int shape, hipStream_t s) {
+  NosArgs a;
+  a.eps = eps;
+  a.w = w;
+  a.w_scale = w_scale;
+  a.out = out;
+  a.n1 = d.n1;
+  a.n2 = d.n2;
+  a.n3 = d.n3;
+  a.e0 = d.e0;
+  a.de = d.de;
+  a.inv_de = 1.0f / d.de;
+  a.V = (float)(1.0 / (24.0 * (double)d.n1 * d.n2 * d.n3));  // V_T / (4 V_G)
+  a.nout = d.ne;
+  if (binned) {  // increments between the midpoints E_j -+ de/2: ne + 1 grid indices, the first dropped
+    a.ng = d.ne + 1;
+    a.joff = -0.5f;
+    a.shift = 1;
+    a.out_scale = 1.0 / (double)d.de;
+  } else {
+    a.ng = d.ne;
+    a.joff = 0.0f;
+    a.shift = 0;
+    a.out_scale = 1.0;
+  }
+  const TileShape sh = tile_shape(shape);
+  a.TX = sh.x;
+  a.TY = sh.y;
+  a.TZ = sh.z;
+  a.t1 = (d.n1 + sh.x - 1) / sh.x;
+  a.t2 = (d.n2 + sh.y - 1) / sh.y;
+  a.t3 = (d.n3 + sh.z - 1) / sh.z;
+  a.ntiles = a.t1 * a.t2 * a.t3;
+  a.nunits = a.ntiles * d.nb;
+  a.per_xcd = (a.nunits + NXCD - 1) / NXCD;
+  const int grid = a.per_xcd * NXCD;
+  hipError_t e = fill_zero(out, (int64_t)d.ne * d.norb, s);
+  if (e != hipSuccess) return e;
+  switch (d.norb) {
+#define TETRA_CASE(N)           \
+  case N:                       \
+    e = launch_nos<N>(a, grid, s); \
+    break;
+    TETRA_CASE(1) TETRA_CASE(2) TETRA_CASE(3) TETRA_CASE(4) TETRA_CASE(5) TETRA_CASE(6) TETRA_CASE(7)
+    TETRA_CASE(8) TETRA_CASE(9) TETRA_CASE(10) TETRA_CASE(11) TETRA_CASE(12) TETRA_CASE(13)
+    TETRA_CASE(14) TETRA_CASE(15) TETRA_CASE(16)
+#undef TETRA_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess || binned) return e;
+  hipLaunchKernelGGL(column_scan_kernel, dim3(d.norb), dim3(256), 0, s, out, d.ne, d.norb);
+  return hipGetLastError();
+}
+
+}  // namespace tetra

@@ -15,10 +15,13 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <random>
 
 #include "tetra_device.h"
+#include "tetra_nos_device.h"
 
+extern "C" void tetra_oracle_corner_weights(const double e_sorted[4], double E, double vol, double w[4], double g[4]);
 extern "C" void tetra_oracle_corner_weights_grad(const double e_sorted[4], double E, double vol, double g[4],
                                                  double dg[16]);
 
@@ -129,5 +132,64 @@ int main(int argc, char** argv) {
   const char* names[3] = {"first", "middle", "third"};
   for (int k = 0; k < 3; ++k)
     std::printf("%s %ld %.6e %.6e %.6e %.6e\n", names[k], ranges[k], werr[k], eerr[k][0], eerr[k][1], berr[k]);
+
+  // Integrated weights (number of states) as the kernel forms them: the exact steps ja (first E_j > E1)
+  // and js (first E_j >= E4) of step_window, the case split of the window [ja, js), the case
+  // polynomials, and V from js on, on the grid E_j = e0 + (j + joff) de for joff = 0 and -1/2 (the
+  // bin midpoints). Compared with the oracle's w_l(E_j) for every j from ja - 2 to js + 1, relative
+  // to V; a step index that disagrees with the FP64 comparison by more than FP32 rounding is counted.
+  for (int half = 0; half < 2; ++half) {
+    const float joff = half ? -0.5f : 0.0f;
+    double nerr = 0.0;
+    long npts = 0, nbad = 0;
+    for (int it = 0; it < n; ++it) {
+      float e[4];
+      for (int l = 0; l < 4; ++l) e[l] = U(rng);
+      const int kind = it % 4;
+      if (kind > 0) e[kind] = e[kind - 1] + 1.0e-3f * U(rng);
+      if (it % 97 == 0) e[1] = e[0];  // exactly equal neighbours
+      int p[4] = {0, 1, 2, 3};
+      sort4(e, p);
+      const double ed[4] = {e[0], e[1], e[2], e[3]};
+      TetSetup cs = tet_setup(e, e0, V);
+      shift_frames(cs, joff * de);
+      int ja, js;
+      step_window(cs, e[0], e[3], e0, joff, de, 1.0f / de, ja, js);
+      auto Ej = [&](int j) { return (double)e0 + ((double)j + (double)joff) * (double)de; };
+      int ta = ja, ts = js;  // FP64 steps
+      while (Ej(ta) > ed[0]) --ta;
+      while (!(Ej(ta) > ed[0])) ++ta;
+      while (Ej(ts) >= ed[3]) --ts;
+      while (!(Ej(ts) >= ed[3])) ++ts;
+      // a few FP32 roundings of the local frame x_j and of E41
+      const double tol = 1.0e-6 * de + 2.5e-7 * (ed[3] - ed[0]) + 1.2e-7 * std::fabs(Ej(js) - e0);
+      if (ta != ja && std::fabs(Ej(std::min(ta, ja)) - ed[0]) > tol) ++nbad;
+      if (ts != js && std::fabs(Ej(std::min(ts, js)) - ed[3]) > tol) ++nbad;
+      const int lo = std::min(ja, js), jlast = js - 1;
+      int jA = lo - 1, jB = lo - 1;
+      if (jlast >= lo) case_split(cs, de, 1.0f / de, lo, jlast, jA, jB);
+      float coef[4][5];
+      corner_nos_B_coeffs(cs, V, coef);
+      for (int j = lo - 2; j <= js + 1; ++j) {
+        float w[4];
+        if (j < lo) {
+          for (int l = 0; l < 4; ++l) w[l] = 0.0f;
+        } else if (j >= js) {
+          for (int l = 0; l < 4; ++l) w[l] = V;
+        } else if (j <= jA) {
+          corner_nos_A(cs, local_x(cs, j, de), w);
+        } else if (j <= jB) {
+          corner_nos_B_poly(coef, local_z(cs, j, de), w);
+        } else {
+          corner_nos_C(cs, V, local_y(cs, j, de), w);
+        }
+        double wr[4], gr[4];
+        tetra_oracle_corner_weights(ed, Ej(j), 4.0 * V, wr, gr);
+        for (int l = 0; l < 4; ++l) nerr = std::fmax(nerr, std::isfinite(w[l]) ? std::fabs(w[l] - wr[l]) / V : INFINITY);
+        ++npts;
+      }
+    }
+    std::printf("%s %ld %.6e %ld\n", half ? "nos_half" : "nos", npts, nerr, nbad);
+  }
   return 0;
 }

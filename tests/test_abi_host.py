@@ -30,7 +30,8 @@ def L():
 def test_header_declares_the_entry_points():
     names = _declared_functions()
     for n in ("tetra_dos_forward", "tetra_dos_backward", "tetra_dos_batched", "tetra_dos_batched_workspace",
-              "tetra_status_string", "tetra_last_hip_error", "tetra_version"):
+              "tetra_nos_forward", "tetra_dos_binned", "tetra_status_string", "tetra_last_hip_error",
+              "tetra_version"):
         assert n in names
 
 
@@ -105,6 +106,32 @@ def test_backward_rejects_bad_arguments(L):
     assert _bwd(L, good(), flags=4) == -1
     assert _bwd(L, good(), flags=9 << 8) == -1
     assert _bwd(L, good(), flags=2) == -2  # no deterministic adjoint
+
+
+@pytest.mark.parametrize("name", ["tetra_nos_forward", "tetra_dos_binned"])
+def test_number_of_states_rejects_bad_arguments(L, name):
+    f = getattr(L, name)
+
+    def call(d=None, eps=FAKE, w=FAKE, wtype=0, scale=None, out=FAKE, flags=0):
+        d = good() if d is None else d
+        return f(ctypes.byref(d), eps, w, wtype, scale, out, flags, None)
+
+    assert f(None, FAKE, FAKE, 0, None, FAKE, 0, None) == -1
+    assert call(eps=None) == -1
+    assert call(w=None) == -1
+    assert call(out=None) == -1
+    assert call(wtype=1) == -1  # FP16 weights need a scale
+    assert call(scale=FAKE) == -1  # FP32 weights take no scale
+    assert call(flags=4) == -1
+    assert call(flags=6 << 8) == -1  # no such tile shape
+    assert call(flags=1) == -2  # no exact mode
+    assert call(flags=2) == -2
+    d = good()
+    d.ne = 0
+    assert call(d=d) == -1
+    d = good()
+    d.norb = 17
+    assert call(d=d) == -2
 
 
 def test_batched_rejects_bad_arguments(L):

@@ -1,12 +1,15 @@
 """The kernels' per-tetrahedron arithmetic (``tetra_device.h``: sort, windows, case split, corner weights
-in their local frames, the middle case's cubic form, and the range-end adjoint from power sums of the
-loss gradient) built for the host with g++ and checked against the FP64 oracle's corner weights and
-dual-number energy derivatives on random tetrahedra, generic and with nearly equal corner energies.
+in their local frames, the middle case's cubic form, the range-end adjoint from power sums of the
+loss gradient, and the integrated weights of the number of states with their step indices, on the
+grid and on the midpoints between grid energies) built for the host with g++ and checked against the
+FP64 oracle's corner weights and dual-number energy derivatives on random tetrahedra, generic and
+with nearly equal corner energies.
 No GPU needed; the harness is test code only.
 
 Bounds (FP32 arithmetic against FP64): corner weights within 1e-5 of the tetrahedron's largest
 weight; a case range's energy gradient within 5e-4 of the sum of its per-energy |derivatives|, and its
-weight gradient within 1e-5 of sum_j |G| |g| (a sign or index mistake in any term gives O(1))."""
+weight gradient within 1e-5 of sum_j |G| |g|; integrated weights within 1e-5 of V_T/(4 V_G) (a sign or
+index mistake in any term gives O(1))."""
 import os
 import shutil
 import subprocess
@@ -40,6 +43,16 @@ def test_corner_weights_and_moment_adjoint_against_oracle(harness):
         if len(parts) == 6:
             rows[parts[0]] = (int(parts[1]), *map(float, parts[2:]))
     print(res.stdout)
+    nos = {}
+    for line in res.stdout.split("\n"):
+        parts = line.split()
+        if len(parts) == 4:
+            nos[parts[0]] = (int(parts[1]), float(parts[2]), int(parts[3]))
+    assert set(nos) == {"nos", "nos_half"}
+    for grid, (npts, err, bad) in nos.items():
+        assert npts > 100000, grid
+        assert err <= 1e-5, (grid, err)  # integrated weights, relative to V_T/(4 V_G)
+        assert bad == 0, grid  # number-of-states steps at the right grid indices
     assert set(rows) == {"first", "middle", "third"}
     for case, (n, werr, gen, deg, berr) in rows.items():
         assert n > 1000, case

@@ -213,7 +213,8 @@ def test_histogram_convergence_cosine_band(oracle_lib):
     for N in (6, 12, 24):
         eps, w = synth.cosine_band((N, N, N))
         nos = oracle_lib.nos(eps, w, (N, N, N), edges[0], width, len(edges))
-        binned = np.diff(nos[:, 0]) / width
+        binned = oracle_lib.dos_binned(eps, w, (N, N, N), edges[0] + 0.5 * width, width, len(edges) - 1)[:, 0]
+        np.testing.assert_allclose(binned, np.diff(nos[:, 0]) / width, rtol=1e-12, atol=1e-12)
         errs.append(np.abs(binned - hist).sum() * width)
     assert errs[0] > errs[1] > errs[2]
     assert errs[2] < 0.02
@@ -228,3 +229,34 @@ def test_bench_window_count_matches_oracle(oracle_lib):
         e0, de = synth.energy_grid(eps, ne)
         _, cnt = oracle_lib.dos(eps, w, grid, e0, de, ne)
         assert bench.count_window_updates(eps, grid, e0, de, ne) == cnt
+
+
+def test_bench_step_count_brute_force():
+    """The benchmark's number-of-states update count (the unit of its roofline): per tetrahedron-band,
+    the grid indices from the first E_j > E1 to the first E_j >= E4, clipped to the grid with
+    everything below it at index 0; brute force over the tetrahedra of a small grid."""
+    import bench
+
+    grid, ne = (5, 3, 4), 37
+    eps, _ = synth.band_structure(3, 2, grid)
+    n1, n2, n3 = grid
+    lo, hi = float(eps.min()), float(eps.max())
+    for origin_frac, joff in ((0.3, 0.0), (-0.2, -0.5), (0.9, 0.0)):
+        e0 = float(np.float32(lo + origin_frac * (hi - lo)))
+        de = float(np.float32(0.6 * (hi - lo) / ne))
+        E = e0 + (np.arange(ne) + joff) * de
+        want = 0
+        for n in range(eps.shape[0]):
+            for i1 in range(n1):
+                for i2 in range(n2):
+                    for i3 in range(n3):
+                        for tet in bench.table1_offsets():
+                            c = [eps[n, ((i1 + o[0]) % n1 * n2 + (i2 + o[1]) % n2) * n3 + (i3 + o[2]) % n3] for o in tet]
+                            e1, e4 = float(min(c)), float(max(c))
+                            above = np.nonzero(E > e1)[0]
+                            ja = above[0] if len(above) else ne
+                            reach = np.nonzero(E >= e4)[0]
+                            js = reach[0] if len(reach) else ne
+                            if ja < ne or js < ne:
+                                want += min(js, ne - 1) - min(ja, js) + 1
+        assert bench.count_step_updates(eps, grid, e0, de, ne, joff) == want
