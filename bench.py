@@ -40,9 +40,9 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 KERNEL_SOURCES = {
-    "dos_forward_kernel": ("tetra_forward.hip", "tetra_device.h", "tetra_internal.h"),
-    "dos_backward_kernel": ("tetra_backward.hip", "tetra_device.h", "tetra_internal.h"),
-    "nos_kernel": ("tetra_nos.hip", "tetra_nos_device.h", "tetra_device.h", "tetra_internal.h"),
+    "dos_forward_kernel": ("tetra_forward.hip", "tetra_device.h", "tetra_internal.h", "tetra_weights.h"),
+    "dos_backward_kernel": ("tetra_backward.hip", "tetra_device.h", "tetra_internal.h", "tetra_weights.h"),
+    "nos_kernel": ("tetra_nos.hip", "tetra_nos_device.h", "tetra_device.h", "tetra_internal.h", "tetra_weights.h"),
 }
 
 

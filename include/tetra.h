@@ -56,7 +56,10 @@ typedef enum {
 /* Storage type of the orbital weights w. */
 typedef enum {
   TETRA_W_F32 = 0, /* float w[nb][norb][nk]; w_scale must be NULL */
-  TETRA_W_F16 = 1  /* _Float16/half w[nb][norb][nk]; value = w * w_scale[n] (per band) */
+  TETRA_W_F16 = 1, /* _Float16/half w[nb][norb][nk]; value = w * w_scale[n] (per band) */
+  TETRA_W_C32 = 2  /* complex amplitudes a^m_n(k) as interleaved float pairs (re, im), w[nb][norb][nk][2];
+                      value b = re^2 + im^2 (eq. matrixelements), formed in the kernels as the paper's
+                      kernel does from eigenvector components; w_scale must be NULL */
 } tetra_wtype;
 
 /* Flag bits. */
@@ -94,8 +97,8 @@ typedef struct {
  * Orbital-resolved DOS (Sec. II.C, eq. tetmethoorbitalresolved).
  *   d        host descriptor
  *   eps      device, float [nb][nk]        band energies E_n(k)
- *   w        device, [nb][norb][nk]        orbital weights b_mn(k) (type by wtype)
- *   wtype    TETRA_W_F32 or TETRA_W_F16
+ *   w        device, [nb][norb][nk]        orbital weights b_mn(k), or amplitudes a^m_n(k) (type by wtype)
+ *   wtype    TETRA_W_F32, TETRA_W_F16 or TETRA_W_C32
  *   w_scale  device, float [nb]            per-band scale for TETRA_W_F16, else NULL
  *   dos      device, float [ne][norb]      result, overwritten
  *   flags    TETRA_KAHAN, TETRA_DETERMINISTIC, TETRA_TILE(shape), or 0
@@ -111,7 +114,9 @@ tetra_status tetra_dos_forward(const tetra_desc* d, const float* eps, const void
  *   grad_dos  device, float [ne][norb]     G
  *   grad_eps  device, float [nb][nk]       dL/deps, overwritten; may be NULL
  *   grad_w    device, float [nb][norb][nk] dL/dw (always FP32, of the dequantised weights),
- *                                           overwritten; may be NULL
+ *                                           overwritten; may be NULL. For TETRA_W_C32 it is
+ *                                           float [nb][norb][nk][2]: dL/d(re a), dL/d(im a)
+ *                                           = 2 (re a, im a) dL/db, interleaved like the input
  *   flags     TETRA_TILE(shape) or 0; TETRA_KAHAN is accepted and ignored (each output element sums at
  *             most eight partial values); TETRA_DETERMINISTIC gives TETRA_ERR_UNSUPPORTED
  * At least one of grad_eps, grad_w must be non-NULL. Where an energy E_j equals a corner energy the

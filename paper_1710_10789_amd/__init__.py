@@ -18,6 +18,7 @@ __all__ = [
     "TETRA_KAHAN",
     "TETRA_W_F32",
     "TETRA_W_F16",
+    "TETRA_W_C32",
     "library_path",
     "lib",
     "make_desc",
@@ -38,6 +39,7 @@ _LIB_PATH = os.path.join(_PKG, "libtetra.so")
 TETRA_OK = 0
 TETRA_W_F32 = 0
 TETRA_W_F16 = 1
+TETRA_W_C32 = 2
 TETRA_KAHAN = 1
 TETRA_DETERMINISTIC = 2
 MAX_NORB = 16
@@ -178,8 +180,16 @@ def _shapes(eps, w, grid):
     return nk, nb, norb
 
 
+def _weight_dtypes(torch):
+    return (torch.float32, torch.float16, torch.complex64)
+
+
+def _wtype_of(torch, w):
+    return {torch.float16: TETRA_W_F16, torch.complex64: TETRA_W_C32}.get(w.dtype, TETRA_W_F32)
+
+
 def _weights_type(torch, w, w_scale, nb, dev):
-    wtype = TETRA_W_F16 if w.dtype == torch.float16 else TETRA_W_F32
+    wtype = _wtype_of(torch, w)
     if wtype == TETRA_W_F16:
         if w_scale is None:
             raise ValueError("float16 weights need w_scale")
@@ -194,7 +204,7 @@ def _integrated(func, eps, w, grid, e0, de, ne, w_scale, out, tile):
     nk, nb, norb = _shapes(eps, w, grid)
     dev = eps.device
     _require(eps, "eps", (nb, nk), (torch.float32,), dev)
-    _require(w, "w", (nb, norb, nk), (torch.float32, torch.float16), dev)
+    _require(w, "w", (nb, norb, nk), _weight_dtypes(torch), dev)
     wtype = _weights_type(torch, w, w_scale, nb, dev)
     if out is None:
         out = torch.empty((int(ne), norb), dtype=torch.float32, device=dev)
@@ -224,8 +234,9 @@ def dos_binned(eps, w, grid, e0, de, ne, *, w_scale=None, out=None, tile=None):
 def dos_forward(eps, w, grid, e0, de, ne, *, w_scale=None, kahan=False, deterministic=False, out=None, tile=None):
     """Orbital-resolved DOS ``[ne, norb]`` (FP32) on the current HIP stream.
 
-    eps: float32 ``[nb, nk]``; w: float32 or float16 ``[nb, norb, nk]`` (float16 needs ``w_scale``
-    float32 ``[nb]``); grid: (n1, n2, n3) with nk = n1*n2*n3; E_j = e0 + j*de. ``kahan`` selects the
+    eps: float32 ``[nb, nk]``; w: float32 or float16 orbital weights ``[nb, norb, nk]`` (float16 needs
+    ``w_scale`` float32 ``[nb]``), or complex64 amplitudes a (the weights are ``|a|^2``, formed in the
+    kernels); grid: (n1, n2, n3) with nk = n1*n2*n3; E_j = e0 + j*de. ``kahan`` selects the
     exact cross-workgroup accumulation, ``deterministic`` asks for a bitwise reproducible result (the
     same exact path); ``tile`` an index into ``TILE_SHAPES`` (default 0).
     """
@@ -233,14 +244,8 @@ def dos_forward(eps, w, grid, e0, de, ne, *, w_scale=None, kahan=False, determin
     nk, nb, norb = _shapes(eps, w, grid)
     dev = eps.device
     _require(eps, "eps", (nb, nk), (torch.float32,), dev)
-    _require(w, "w", (nb, norb, nk), (torch.float32, torch.float16), dev)
-    wtype = TETRA_W_F16 if w.dtype == torch.float16 else TETRA_W_F32
-    if wtype == TETRA_W_F16:
-        if w_scale is None:
-            raise ValueError("float16 weights need w_scale")
-        _require(w_scale, "w_scale", (nb,), (torch.float32,), dev)
-    elif w_scale is not None:
-        raise ValueError("w_scale is only used with float16 weights")
+    _require(w, "w", (nb, norb, nk), _weight_dtypes(torch), dev)
+    wtype = _weights_type(torch, w, w_scale, nb, dev)
     if out is None:
         out = torch.empty((int(ne), norb), dtype=torch.float32, device=dev)
     _require(out, "out", (int(ne), norb), (torch.float32,), dev)
@@ -256,25 +261,27 @@ def dos_forward(eps, w, grid, e0, de, ne, *, w_scale=None, kahan=False, determin
 
 def dos_backward(eps, w, grid, e0, de, grad_dos, *, w_scale=None, need_eps=True, need_w=True,
                  grad_eps=None, grad_w=None, tile=None):
-    """``(dL/deps [nb, nk] or None, dL/dw [nb, norb, nk] float32 or None)`` for ``grad_dos = dL/dDOS``."""
+    """``(dL/deps [nb, nk] or None, dL/dw [nb, norb, nk] or None)`` for ``grad_dos = dL/dDOS``.
+
+    dL/dw is float32 for float32 or float16 weights (of the dequantised weights) and complex64 for
+    complex amplitudes, ``2 a dL/db`` (the gradient with respect to the real and imaginary parts)."""
     torch = _torch()
     nk, nb, norb = _shapes(eps, w, grid)
     dev = eps.device
     ne = grad_dos.shape[0]
     _require(eps, "eps", (nb, nk), (torch.float32,), dev)
-    _require(w, "w", (nb, norb, nk), (torch.float32, torch.float16), dev)
+    _require(w, "w", (nb, norb, nk), _weight_dtypes(torch), dev)
     _require(grad_dos, "grad_dos", (ne, norb), (torch.float32,), dev)
-    wtype = TETRA_W_F16 if w.dtype == torch.float16 else TETRA_W_F32
-    if wtype == TETRA_W_F16:
-        _require(w_scale, "w_scale", (nb,), (torch.float32,), dev)
+    wtype = _weights_type(torch, w, w_scale, nb, dev)
+    gw_dtype = torch.complex64 if wtype == TETRA_W_C32 else torch.float32
     if need_eps and grad_eps is None:
         grad_eps = torch.empty((nb, nk), dtype=torch.float32, device=dev)
     if need_w and grad_w is None:
-        grad_w = torch.empty((nb, norb, nk), dtype=torch.float32, device=dev)
+        grad_w = torch.empty((nb, norb, nk), dtype=gw_dtype, device=dev)
     if grad_eps is not None:
         _require(grad_eps, "grad_eps", (nb, nk), (torch.float32,), dev)
     if grad_w is not None:
-        _require(grad_w, "grad_w", (nb, norb, nk), (torch.float32,), dev)
+        _require(grad_w, "grad_w", (nb, norb, nk), (gw_dtype,), dev)
     d = make_desc(grid, nb, norb, e0, de, ne)
     st = lib().tetra_dos_backward(
         ctypes.byref(d), eps.data_ptr(), w.data_ptr(), wtype,
@@ -297,8 +304,8 @@ def _batch_items(problems, out, tiles=None):
         nk, nb, norb = _shapes(eps, w, grid)
         dev = eps.device
         _require(eps, f"items[{i}].eps", (nb, nk), (torch.float32,), dev)
-        _require(w, f"items[{i}].w", (nb, norb, nk), (torch.float32, torch.float16), dev)
-        wt = TETRA_W_F16 if w.dtype == torch.float16 else TETRA_W_F32
+        _require(w, f"items[{i}].w", (nb, norb, nk), _weight_dtypes(torch), dev)
+        wt = _wtype_of(torch, w)
         if wtype is None:
             wtype = wt
         elif wt != wtype:
@@ -376,7 +383,7 @@ _FN = None
 
 
 def dos(eps, w, grid, e0, de, ne, kahan=False, tile=None, backward_tile=None):
-    """Differentiable orbital-resolved DOS ``[ne, norb]`` (FP32 weights).
+    """Differentiable orbital-resolved DOS ``[ne, norb]`` (float32 weights or complex64 amplitudes).
 
     Gradients with respect to ``eps`` and ``w`` come from the adjoint kernel.
     """
@@ -386,13 +393,18 @@ def dos(eps, w, grid, e0, de, ne, kahan=False, tile=None, backward_tile=None):
     return _FN.apply(eps, w, tuple(grid), e0, de, ne, kahan, (tile, backward_tile))
 
 
-def from_eigh(evals, evecs):
+def from_eigh(evals, evecs, amplitudes=False):
     """Structure-of-arrays inputs from ``torch.linalg.eigh`` output.
 
-    evals ``[nk, nb]`` and eigenvectors ``[nk, norb, nb]`` (columns are bands) -> eps ``[nb, nk]``,
-    w ``[nb, norb, nk]`` with w = |a|^2 (eq. matrixelements). Differentiable; not part of the DOS path.
+    evals ``[nk, nb]`` and eigenvectors ``[nk, norb, nb]`` (columns are bands) -> eps ``[nb, nk]`` and
+    w ``[nb, norb, nk]``: the weights |a|^2 (eq. matrixelements) in float32, or with ``amplitudes`` the
+    eigenvector components a themselves in complex64 (the kernels square them). Differentiable (a
+    layout change); not part of the DOS path.
     """
     eps = evals.transpose(0, 1).contiguous().float()
+    if amplitudes:
+        a = evecs if evecs.is_complex() else evecs.to(_torch().complex64)
+        return eps, a.permute(2, 1, 0).contiguous().to(_torch().complex64)
     w = (evecs.real ** 2 + evecs.imag ** 2) if evecs.is_complex() else evecs ** 2
     return eps, w.permute(2, 1, 0).contiguous().float()
 

@@ -67,10 +67,12 @@ tetra_status check_desc(const tetra_desc* d) {
 }
 
 tetra_status check_weights(int wtype, const float* w_scale) {
-  if (wtype == TETRA_W_F32) return w_scale ? TETRA_ERR_ARG : TETRA_OK;
+  if (wtype == TETRA_W_F32 || wtype == TETRA_W_C32) return w_scale ? TETRA_ERR_ARG : TETRA_OK;
   if (wtype == TETRA_W_F16) return w_scale ? TETRA_OK : TETRA_ERR_ARG;
   return TETRA_ERR_ARG;
 }
+
+const float* scale_of(int wtype, const float* w_scale) { return wtype == TETRA_W_F16 ? w_scale : nullptr; }
 
 }  // namespace
 
@@ -94,7 +96,7 @@ tetra_status tetra_dos_forward(const tetra_desc* d, const float* eps, const void
     if (e != hipSuccess) return hip_status(e);
   }
   return hip_status(
-      tetra::forward(*d, eps, w, wtype == TETRA_W_F16 ? w_scale : nullptr, dos, scratch, shape, (hipStream_t)stream));
+      tetra::forward(*d, eps, w, wtype, scale_of(wtype, w_scale), dos, scratch, shape, (hipStream_t)stream));
 }
 
 tetra_status tetra_dos_backward(const tetra_desc* d, const float* eps, const void* w, int wtype,
@@ -108,8 +110,8 @@ tetra_status tetra_dos_backward(const tetra_desc* d, const float* eps, const voi
   const int shape = (int)((flags & TETRA_TILE_MASK) >> 8);
   if (shape >= tetra::kTileShapes) return TETRA_ERR_ARG;
   if (flags & TETRA_DETERMINISTIC) return TETRA_ERR_UNSUPPORTED;
-  return hip_status(tetra::backward(*d, eps, w, wtype == TETRA_W_F16 ? w_scale : nullptr, grad_dos, grad_eps,
-                                    grad_w, shape, (hipStream_t)stream));
+  return hip_status(tetra::backward(*d, eps, w, wtype, scale_of(wtype, w_scale), grad_dos, grad_eps, grad_w, shape,
+                                    (hipStream_t)stream));
 }
 
 namespace {
@@ -124,8 +126,7 @@ tetra_status nos_entry(const tetra_desc* d, const float* eps, const void* w, int
   const int shape = (int)((flags & TETRA_TILE_MASK) >> 8);
   if (shape >= tetra::kTileShapes) return TETRA_ERR_ARG;
   if (flags & (TETRA_KAHAN | TETRA_DETERMINISTIC)) return TETRA_ERR_UNSUPPORTED;
-  return hip_status(tetra::nos(*d, eps, w, wtype == TETRA_W_F16 ? w_scale : nullptr, out, binned, shape,
-                               (hipStream_t)stream));
+  return hip_status(tetra::nos(*d, eps, w, wtype, scale_of(wtype, w_scale), out, binned, shape, (hipStream_t)stream));
 }
 
 }  // namespace
@@ -141,7 +142,8 @@ tetra_status tetra_dos_binned(const tetra_desc* d, const float* eps, const void*
 }
 
 size_t tetra_dos_batched_workspace(const tetra_item* items, int n, int wtype, unsigned flags) {
-  if (!items || n < 1 || (wtype != TETRA_W_F32 && wtype != TETRA_W_F16) || flags != 0) return 0;
+  if (!items || n < 1 || (wtype != TETRA_W_F32 && wtype != TETRA_W_F16 && wtype != TETRA_W_C32) || flags != 0)
+    return 0;
   for (int i = 0; i < n; ++i)
     if (check_desc(&items[i].d) != TETRA_OK) return 0;
   return 256 * tetra::batched_launches(items, n);
@@ -150,7 +152,7 @@ size_t tetra_dos_batched_workspace(const tetra_item* items, int n, int wtype, un
 tetra_status tetra_dos_batched(const tetra_item* items, int n, int wtype, unsigned flags, void* workspace,
                                size_t ws_bytes, void* stream) {
   if (!items || n < 1) return TETRA_ERR_ARG;
-  if (wtype != TETRA_W_F32 && wtype != TETRA_W_F16) return TETRA_ERR_ARG;
+  if (wtype != TETRA_W_F32 && wtype != TETRA_W_F16 && wtype != TETRA_W_C32) return TETRA_ERR_ARG;
   if (flags & ~(unsigned)(TETRA_KAHAN | TETRA_DETERMINISTIC)) return TETRA_ERR_ARG;
   for (int i = 0; i < n; ++i) {
     const tetra_item& it = items[i];
@@ -164,7 +166,7 @@ tetra_status tetra_dos_batched(const tetra_item* items, int n, int wtype, unsign
   if (!workspace || ws_bytes < 256 * tetra::batched_launches(items, n)) return TETRA_ERR_WORKSPACE;
   std::vector<int> shapes(n);
   for (int i = 0; i < n; ++i) shapes[i] = items[i].tile;
-  return hip_status(tetra::batched(items, shapes.data(), n, wtype == TETRA_W_F16, workspace, (hipStream_t)stream));
+  return hip_status(tetra::batched(items, shapes.data(), n, wtype, workspace, (hipStream_t)stream));
 }
 
 const char* tetra_status_string(int status) {

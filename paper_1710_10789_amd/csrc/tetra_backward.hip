@@ -18,8 +18,11 @@
 // value (the outputs are zero-filled first). On an axis short enough for the periodic wrap to repeat
 // a point inside one tile, every point goes through the atomics, which sums the repeats.
 
+#include <type_traits>
+
 #include "tetra_device.h"
 #include "tetra_internal.h"
+#include "tetra_weights.h"
 
 namespace tetra {
 
@@ -32,11 +35,12 @@ constexpr int NXCD = 8;
 
 struct BwdArgs {
   const float* eps;
-  const void* w;        // float or _Float16 [nb][norb][nk]
+  const void* w;        // float, _Float16 or float2 (complex amplitude) [nb][norb][nk]
   const float* w_scale;  // per-band scale of _Float16 weights
   const float* G;
   float* grad_eps;
-  float* grad_w;
+  float* grad_w;  // [nb][norb][nk], or [nb][norb][nk][2] (re, im) for complex amplitudes
+  int wtype;
   int n1, n2, n3, ne;
   float e0, de, inv_de, V;
   int TX, TY, TZ;  // cubes per tile along grid axes 1, 2, 3 (TX*TY*TZ = NT)
@@ -98,7 +102,7 @@ __global__ __launch_bounds__(NT) void dos_backward_kernel(BwdArgs a) {
       lmax = fmaxf(lmax, e);
     }
 #pragma unroll
-    for (int m = 0; m < NORB; ++m) s_w[p * NORB + m] = (float)w_n[(int64_t)m * nk + k] * wscale;
+    for (int m = 0; m < NORB; ++m) s_w[p * NORB + m] = weight_value(w_n[(int64_t)m * nk + k], wscale);
   }
   lmin = wave_min(lmin);
   lmax = wave_max(lmax);
@@ -283,9 +287,22 @@ __global__ __launch_bounds__(NT) void dos_backward_kernel(BwdArgs a) {
     if (a.grad_w) {
 #pragma unroll
       for (int m = 0; m < NORB; ++m) {
-        float* dst = &a.grad_w[((int64_t)band * NORB + m) * nk + k];
-        if (interior) *dst = src[1 + m];
-        else if (src[1 + m] != 0.0f) unsafeAtomicAdd(dst, src[1 + m]);
+        if constexpr (std::is_same<WT, float2>::value) {
+          // b = re^2 + im^2: dL/d(re, im) = 2 (re, im) dL/db, linear in each partial sum
+          const float2 amp = w_n[(int64_t)m * nk + k];
+          const float g2 = 2.0f * src[1 + m];
+          float* dst = &a.grad_w[2 * (((int64_t)band * NORB + m) * nk + k)];
+          if (interior) {
+            *reinterpret_cast<float2*>(dst) = make_float2(g2 * amp.x, g2 * amp.y);
+          } else if (g2 != 0.0f) {
+            unsafeAtomicAdd(dst, g2 * amp.x);
+            unsafeAtomicAdd(dst + 1, g2 * amp.y);
+          }
+        } else {
+          float* dst = &a.grad_w[((int64_t)band * NORB + m) * nk + k];
+          if (interior) *dst = src[1 + m];
+          else if (src[1 + m] != 0.0f) unsafeAtomicAdd(dst, src[1 + m]);
+        }
       }
     }
   }
@@ -293,8 +310,10 @@ __global__ __launch_bounds__(NT) void dos_backward_kernel(BwdArgs a) {
 
 template <int NORB>
 hipError_t launch_bwd(const BwdArgs& a, int grid, hipStream_t s) {
-  if (a.w_scale)
+  if (a.wtype == TETRA_W_F16)
     hipLaunchKernelGGL((dos_backward_kernel<NORB, _Float16>), dim3(grid), dim3(NT), 0, s, a);
+  else if (a.wtype == TETRA_W_C32)
+    hipLaunchKernelGGL((dos_backward_kernel<NORB, float2>), dim3(grid), dim3(NT), 0, s, a);
   else
     hipLaunchKernelGGL((dos_backward_kernel<NORB, float>), dim3(grid), dim3(NT), 0, s, a);
   return hipGetLastError();
@@ -302,9 +321,10 @@ hipError_t launch_bwd(const BwdArgs& a, int grid, hipStream_t s) {
 
 }  // namespace
 
-hipError_t backward(const tetra_desc& d, const float* eps, const void* w, const float* w_scale, const float* G,
-                    float* grad_eps, float* grad_w, int shape, hipStream_t s) {
+hipError_t backward(const tetra_desc& d, const float* eps, const void* w, int wtype, const float* w_scale,
+                    const float* G, float* grad_eps, float* grad_w, int shape, hipStream_t s) {
   BwdArgs a;
+  a.wtype = wtype;
   a.eps = eps;
   a.w = w;
   a.w_scale = w_scale;
@@ -333,7 +353,7 @@ hipError_t backward(const tetra_desc& d, const float* eps, const void* w, const 
   const int64_t nk = (int64_t)d.n1 * d.n2 * d.n3;
   hipError_t e = hipSuccess;
   if (grad_eps) e = fill_zero(grad_eps, nk * d.nb, s);
-  if (e == hipSuccess && grad_w) e = fill_zero(grad_w, nk * d.nb * d.norb, s);
+  if (e == hipSuccess && grad_w) e = fill_zero(grad_w, nk * d.nb * d.norb * (wtype == TETRA_W_C32 ? 2 : 1), s);
   if (e != hipSuccess) return e;
   switch (d.norb) {
 #define TETRA_CASE(N) \

@@ -33,6 +33,7 @@
 
 #include "tetra_device.h"
 #include "tetra_internal.h"
+#include "tetra_weights.h"
 
 namespace tetra {
 
@@ -45,11 +46,12 @@ constexpr int NXCD = 8;
 
 struct FwdArgs {
   const float* eps;
-  const void* w;        // float or _Float16 [nb][norb][nk]
+  const void* w;        // float, _Float16 or float2 (complex amplitude) [nb][norb][nk]
   const float* w_scale;  // per-band scale of _Float16 weights
   float* dos;
   float* gbound;                // exact mode: sum of the per-workgroup bounds (accumulated in mode 1)
   unsigned long long* gacc;     // exact mode: [ne][norb] 64-bit fixed-point sums (mode 2)
+  int wtype;  // TETRA_W_* of w
   int n1, n2, n3, ne;
   float e0, de, inv_de, V;
   int TX, TY, TZ;  // cubes per tile along grid axes 1, 2, 3 (TX*TY*TZ = NT)
@@ -122,7 +124,7 @@ __device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
     }
 #pragma unroll
     for (int m = 0; m < NORB; ++m) {
-      const float b = (float)w_n[(int64_t)m * nk + k] * wscale;
+      const float b = weight_value(w_n[(int64_t)m * nk + k], wscale);
       s_w[p * NORB + m] = b;
       lbmax = fmaxf(lbmax, fabsf(b));
       lbmin = fminf(lbmin, b);
@@ -386,6 +388,7 @@ __global__ __launch_bounds__(NT, NORB <= 8 ? 5 : 2) void dos_batched_kernel(Batc
     a.eps = it.eps;
     a.w = it.w;
     a.w_scale = it.w_scale;
+    a.wtype = 0;  // not read by the unit body (the type is the template argument)
     a.dos = it.dos;
     a.gbound = nullptr;
     a.gacc = nullptr;
@@ -419,15 +422,20 @@ __global__ void batched_zero_kernel(BatchArgs b, int norb) {
     it.dos[i] = 0.0f;
 }
 
+template <int NORB, typename WT>
+hipError_t occupancy_batched(int* occ) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, dos_batched_kernel<NORB, WT>, NT, 0);
+}
+
 template <int NORB>
-hipError_t launch_batched(const BatchArgs& b, bool half, hipStream_t s) {
+hipError_t launch_batched(const BatchArgs& b, int wtype, hipStream_t s) {
   hipLaunchKernelGGL(batched_zero_kernel, dim3(64, b.n), dim3(256), 0, s, b, NORB);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   // Persistent grid: resident workgroups per CU times the CU count of the current device (cached
   // per device and weight type; concurrent first calls store the same values).
   constexpr int kDevCache = 64;
-  static std::atomic<int> cache_cus[kDevCache], cache_occ[kDevCache][2];
+  static std::atomic<int> cache_cus[kDevCache], cache_occ[kDevCache][3];
   int dev = 0;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
   const bool cached = dev >= 0 && dev < kDevCache;
@@ -436,17 +444,20 @@ hipError_t launch_batched(const BatchArgs& b, bool half, hipStream_t s) {
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
     if (cached) cache_cus[dev].store(cus, std::memory_order_relaxed);
   }
-  int occ = cached ? cache_occ[dev][half ? 1 : 0].load(std::memory_order_relaxed) : 0;
+  int occ = cached ? cache_occ[dev][wtype].load(std::memory_order_relaxed) : 0;
   if (!occ) {
-    e = half ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, dos_batched_kernel<NORB, _Float16>, NT, 0)
-             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, dos_batched_kernel<NORB, float>, NT, 0);
+    e = wtype == TETRA_W_F16   ? occupancy_batched<NORB, _Float16>(&occ)
+        : wtype == TETRA_W_C32 ? occupancy_batched<NORB, float2>(&occ)
+                               : occupancy_batched<NORB, float>(&occ);
     if (e != hipSuccess) return e;
     if (occ < 1) occ = 1;
-    if (cached) cache_occ[dev][half ? 1 : 0].store(occ, std::memory_order_relaxed);
+    if (cached) cache_occ[dev][wtype].store(occ, std::memory_order_relaxed);
   }
   const int grid = std::min(b.total, occ * cus);
-  if (half)
+  if (wtype == TETRA_W_F16)
     hipLaunchKernelGGL((dos_batched_kernel<NORB, _Float16>), dim3(grid), dim3(NT), 0, s, b);
+  else if (wtype == TETRA_W_C32)
+    hipLaunchKernelGGL((dos_batched_kernel<NORB, float2>), dim3(grid), dim3(NT), 0, s, b);
   else
     hipLaunchKernelGGL((dos_batched_kernel<NORB, float>), dim3(grid), dim3(NT), 0, s, b);
   return hipGetLastError();
@@ -454,8 +465,10 @@ hipError_t launch_batched(const BatchArgs& b, bool half, hipStream_t s) {
 
 template <int NORB, int MODE>
 hipError_t launch_fwd_mode(const FwdArgs& a, int grid, hipStream_t s) {
-  if (a.w_scale)
+  if (a.wtype == TETRA_W_F16)
     hipLaunchKernelGGL((dos_forward_kernel<NORB, _Float16, MODE>), dim3(grid), dim3(NT), 0, s, a);
+  else if (a.wtype == TETRA_W_C32)
+    hipLaunchKernelGGL((dos_forward_kernel<NORB, float2, MODE>), dim3(grid), dim3(NT), 0, s, a);
   else
     hipLaunchKernelGGL((dos_forward_kernel<NORB, float, MODE>), dim3(grid), dim3(NT), 0, s, a);
   return hipGetLastError();
@@ -501,9 +514,10 @@ hipError_t fill_zero(float* p, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t forward(const tetra_desc& d, const float* eps, const void* w, const float* w_scale, float* dos,
+hipError_t forward(const tetra_desc& d, const float* eps, const void* w, int wtype, const float* w_scale, float* dos,
                    void* exact_scratch, int shape, hipStream_t s) {
   FwdArgs a;
+  a.wtype = wtype;
   // exact_scratch (exact mode): 256 bytes holding the bound, then ne*norb 64-bit sums
   a.gbound = exact_scratch ? static_cast<float*>(exact_scratch) : nullptr;
   a.gacc = exact_scratch ? reinterpret_cast<unsigned long long*>(static_cast<char*>(exact_scratch) + 256) : nullptr;
@@ -565,7 +579,7 @@ size_t batched_launches(const tetra_item* items, int n) {
   return launches;
 }
 
-hipError_t batched(const tetra_item* items, const int* shapes, int n, bool half, void* workspace, hipStream_t s) {
+hipError_t batched(const tetra_item* items, const int* shapes, int n, int wtype, void* workspace, hipStream_t s) {
   unsigned* counters = static_cast<unsigned*>(workspace);
   int launch = 0;
   for (int norb = 1; norb <= 16; ++norb) {
@@ -580,7 +594,7 @@ hipError_t batched(const tetra_item* items, const int* shapes, int n, bool half,
         switch (norb) {
 #define TETRA_CASE(N) \
   case N:             \
-    e = launch_batched<N>(b, half, s); \
+    e = launch_batched<N>(b, wtype, s); \
     break;
           TETRA_CASE(1) TETRA_CASE(2) TETRA_CASE(3) TETRA_CASE(4) TETRA_CASE(5) TETRA_CASE(6) TETRA_CASE(7)
           TETRA_CASE(8) TETRA_CASE(9) TETRA_CASE(10) TETRA_CASE(11) TETRA_CASE(12) TETRA_CASE(13)
@@ -599,7 +613,7 @@ hipError_t batched(const tetra_item* items, const int* shapes, int n, bool half,
       BatchItem& it = b.it[b.n++];
       it.eps = items[i].eps;
       it.w = items[i].w;
-      it.w_scale = half ? items[i].w_scale : nullptr;
+      it.w_scale = wtype == TETRA_W_F16 ? items[i].w_scale : nullptr;
       it.dos = items[i].dos;
       it.n1 = d.n1;
       it.n2 = d.n2;

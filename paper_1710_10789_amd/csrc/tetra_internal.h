@@ -26,19 +26,21 @@ __host__ __device__ inline TileShape tile_shape(int id) {
 }
 
 hipError_t fill_zero(float* p, int64_t n, hipStream_t s);
-// w is float, or _Float16 when w_scale (per-band scale) is non-null. exact_scratch (or null) is device
-// memory of forward_exact_scratch_bytes(d) for the exact cross-workgroup accumulation.
-hipError_t forward(const tetra_desc& d, const float* eps, const void* w, const float* w_scale, float* dos,
+// Weights w by wtype: TETRA_W_F32 float, TETRA_W_F16 _Float16 with the per-band w_scale, TETRA_W_C32
+// complex amplitudes (float2). exact_scratch (or null) is device memory of
+// forward_exact_scratch_bytes(d) for the exact cross-workgroup accumulation.
+hipError_t forward(const tetra_desc& d, const float* eps, const void* w, int wtype, const float* w_scale, float* dos,
                    void* exact_scratch, int shape, hipStream_t s);
 // Batched forward: items grouped by orbital count, up to kMaxBatch per persistent launch. The
 // workspace holds one 256-byte work counter per launch.
 size_t batched_launches(const tetra_item* items, int n);
-hipError_t batched(const tetra_item* items, const int* shapes, int n, bool half, void* workspace, hipStream_t s);
+hipError_t batched(const tetra_item* items, const int* shapes, int n, int wtype, void* workspace, hipStream_t s);
 inline size_t forward_exact_scratch_bytes(const tetra_desc& d) { return 256 + 8 * (size_t)d.ne * d.norb; }
 // Number of states (binned = false) or bin-averaged DOS (binned = true) into out[ne][norb].
-hipError_t nos(const tetra_desc& d, const float* eps, const void* w, const float* w_scale, float* out, bool binned,
-               int shape, hipStream_t s);
-hipError_t backward(const tetra_desc& d, const float* eps, const void* w, const float* w_scale, const float* G,
-                    float* grad_eps, float* grad_w, int shape, hipStream_t s);
+hipError_t nos(const tetra_desc& d, const float* eps, const void* w, int wtype, const float* w_scale, float* out,
+               bool binned, int shape, hipStream_t s);
+// grad_w is [nb][norb][nk] floats, or [nb][norb][nk][2] for complex amplitudes.
+hipError_t backward(const tetra_desc& d, const float* eps, const void* w, int wtype, const float* w_scale,
+                    const float* G, float* grad_eps, float* grad_w, int shape, hipStream_t s);
 
 }  // namespace tetra

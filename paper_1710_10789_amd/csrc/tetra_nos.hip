@@ -21,6 +21,7 @@
 // most 4 V bmax per tetrahedron (the increments of one corner add up to V), which fixes the scale.
 
 #include "tetra_internal.h"
+#include "tetra_weights.h"
 #include "tetra_nos_device.h"
 
 namespace tetra {
@@ -34,9 +35,10 @@ constexpr int NXCD = 8;
 
 struct NosArgs {
   const float* eps;
-  const void* w;         // float or _Float16 [nb][norb][nk]
+  const void* w;         // float, _Float16 or float2 (complex amplitude) [nb][norb][nk]
   const float* w_scale;  // per-band scale of _Float16 weights
   float* out;            // [nout][norb]
+  int wtype;
   int n1, n2, n3;
   int ng;      // grid indices j = 0..ng-1 at E_j = e0 + (j + joff) de
   int shift;   // grid index j is written to output row j - shift (rows below 0 are dropped)
@@ -102,7 +104,7 @@ __global__ __launch_bounds__(NT) void nos_kernel(NosArgs a) {
     }
 #pragma unroll
     for (int m = 0; m < NORB; ++m) {
-      const float v = (float)w_n[(int64_t)m * nk + k] * wscale;
+      const float v = weight_value(w_n[(int64_t)m * nk + k], wscale);
       s_w[p * NORB + m] = v;
       lbmax = fmaxf(lbmax, fabsf(v));
       lbmin = fminf(lbmin, v);
@@ -304,8 +306,10 @@ __global__ __launch_bounds__(256) void column_scan_kernel(float* p, int n, int n
 
 template <int NORB>
 hipError_t launch_nos(const NosArgs& a, int grid, hipStream_t s) {
-  if (a.w_scale)
+  if (a.wtype == TETRA_W_F16)
     hipLaunchKernelGGL((nos_kernel<NORB, _Float16>), dim3(grid), dim3(NT), 0, s, a);
+  else if (a.wtype == TETRA_W_C32)
+    hipLaunchKernelGGL((nos_kernel<NORB, float2>), dim3(grid), dim3(NT), 0, s, a);
   else
     hipLaunchKernelGGL((nos_kernel<NORB, float>), dim3(grid), dim3(NT), 0, s, a);
   return hipGetLastError();
@@ -313,9 +317,10 @@ hipError_t launch_nos(const NosArgs& a, int grid, hipStream_t s) {
 
 }  // namespace
 
-hipError_t nos(const tetra_desc& d, const float* eps, const void* w, const float* w_scale, float* out, bool binned,
-               int shape, hipStream_t s) {
+hipError_t nos(const tetra_desc& d, const float* eps, const void* w, int wtype, const float* w_scale, float* out,
+               bool binned, int shape, hipStream_t s) {
   NosArgs a;
+  a.wtype = wtype;
   a.eps = eps;
   a.w = w;
   a.w_scale = w_scale;

@@ -12,10 +12,13 @@ so a random Hermitian tight-binding model of the same shape stands in for it:
 * ``H(k) = sum_R t_R exp(i k.R)`` on a periodic grid ``k_a = 2 pi i_a / N_a``, row-major (i1 slowest);
 * ``eigh`` in complex128 -> ascending band energies ``E_n(k)`` and ``b_mn(k) = |a^m_n(k)|^2``
   (eq. matrixelements), cast to FP32 and laid out structure-of-arrays:
-  ``eps[nb][nk]`` and ``w[nb][norb][nk]`` with ``k = (i1*n2 + i2)*n3 + i3``.
+  ``eps[nb][nk]`` and ``w[nb][norb][nk]`` with ``k = (i1*n2 + i2)*n3 + i3`` (``amplitudes`` gives
+  the eigenvector components ``a[nb][norb][nk]`` themselves, complex64, for small grids).
 """
 from .tb import (
     hoppings,
+    hamiltonians,
+    amplitudes,
     band_structure,
     energy_grid,
     cosine_band,
@@ -27,6 +30,8 @@ from .tb import (
 
 __all__ = [
     "hoppings",
+    "hamiltonians",
+    "amplitudes",
     "band_structure",
     "energy_grid",
     "cosine_band",

@@ -54,6 +54,29 @@ def _diag_chunk(hops, grid, lo, hi):
     return evals, np.abs(evecs) ** 2  # [nc, nb], [nc, norb, nb]
 
 
+def hamiltonians(hops, grid):
+    """Bloch Hamiltonians ``H(k) = sum_R t_R exp(2 pi i k.R)`` ``[nk, norb, norb]`` (complex128) of a
+    hopping set on the periodic grid, k in the library's order (i3 fastest)."""
+    n1, n2, n3 = grid
+    kf = _kfrac(grid, 0, n1 * n2 * n3)
+    t0 = hops[(0, 0, 0)]
+    h = np.empty((kf.shape[0],) + t0.shape, dtype=np.complex128)
+    h[:] = t0
+    for r in _R_POS:
+        ph = np.exp(2j * np.pi * (kf @ np.asarray(r, dtype=np.float64)))
+        h += ph[:, None, None] * hops[r] + ph.conj()[:, None, None] * hops[r].conj().T
+    return h
+
+
+def amplitudes(norb: int, seed: int, grid):
+    """Band energies ``eps [nb, nk]`` (float32) and eigenvector components ``a [nb, norb, nk]``
+    (complex64, a[n, m, k] = <m|n,k>) of the seeded model, for small grids (no cache)."""
+    evals, evecs = np.linalg.eigh(hamiltonians(hoppings(norb, seed), grid))
+    eps = np.ascontiguousarray(evals.T, dtype=np.float32)
+    a = np.ascontiguousarray(evecs.transpose(2, 1, 0), dtype=np.complex64)
+    return eps, a
+
+
 def _cache_path(norb, seed, grid):
     root = os.environ.get("TETRA_SYNTH_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "tetra_synth"))
     tag = hashlib.sha1(repr((_CACHE_VERSION, norb, seed, tuple(grid))).encode()).hexdigest()[:16]

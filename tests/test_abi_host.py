@@ -147,3 +147,30 @@ def test_batched_rejects_bad_arguments(L):
     assert L.tetra_dos_batched(items, 1, 0, 2, FAKE, 4096, None) == -2
     assert L.tetra_dos_batched(items, 1, 0, 0, FAKE, 8, None) == -3  # workspace too small
     assert L.tetra_dos_batched_workspace(items, 1, 0, 0) == 256
+
+
+def test_complex_amplitudes_flags(L):
+    d = good()
+    assert L.tetra_dos_forward(ctypes.byref(d), FAKE, FAKE, 2, FAKE, FAKE, 0, None) == -1  # no scale for C32
+    assert L.tetra_dos_forward(ctypes.byref(d), FAKE, FAKE, 3, None, FAKE, 0, None) == -1  # no such type
+    assert L.tetra_dos_backward(ctypes.byref(d), FAKE, FAKE, 2, FAKE, FAKE, FAKE, FAKE, 0, None) == -1
+    assert L.tetra_nos_forward(ctypes.byref(d), FAKE, FAKE, 2, FAKE, FAKE, 0, None) == -1
+
+
+def test_from_eigh_layouts():
+    """The binding's layout helper (no GPU): eigenvalues [nk, nb] and eigenvectors [nk, norb, nb] to
+    eps [nb, nk] and weights |a|^2 or amplitudes a, both [nb, norb, nk]."""
+    import numpy as np
+    import torch
+
+    rng = np.random.default_rng(0)
+    m = rng.standard_normal((6, 3, 3)) + 1j * rng.standard_normal((6, 3, 3))
+    h = torch.from_numpy(m + np.conj(np.swapaxes(m, 1, 2)))
+    ev, vec = torch.linalg.eigh(h)
+    eps, w = tetra.from_eigh(ev, vec)
+    eps2, a = tetra.from_eigh(ev, vec, amplitudes=True)
+    assert eps.shape == (3, 6) and w.shape == (3, 3, 6) and a.shape == (3, 3, 6)
+    assert a.dtype == torch.complex64 and w.dtype == torch.float32
+    assert torch.equal(eps, eps2)
+    assert torch.allclose(a.abs() ** 2, w, atol=1e-6)
+    assert torch.allclose(a[1, 2, 4].to(torch.complex128), vec[4, 2, 1], atol=1e-6)
