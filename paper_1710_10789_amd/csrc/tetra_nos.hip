@@ -17,8 +17,8 @@
 // band), one lane per cube looping over the six tetrahedra, the tile's grid points staged in LDS, a
 // five-comparator corner sort, and an exact fixed-point LDS histogram over the tile-band's range of
 // grid indices (two orbitals per 64-bit word when the weights are non-negative; every increment is
-// then non-negative too, w_l being non-decreasing in E). A bin's sum over the tile's tetrahedra is at
-// most 4 V bmax per tetrahedron (the increments of one corner add up to V), which fixes the scale.
+// then non-negative too, w_l being non-decreasing in E). A bin's sum over the tile's tetrahedra is
+// bounded per tetrahedron by bmax min(4 V, 12 V de / E41), which fixes the scale.
 
 #include "tetra_internal.h"
 #include "tetra_weights.h"
@@ -62,6 +62,10 @@ __device__ __forceinline__ float wave_min(float v) {
 }
 __device__ __forceinline__ float wave_max(float v) {
   for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
 }
 
@@ -145,6 +149,38 @@ __global__ __launch_bounds__(NT) void nos_kernel(NosArgs a) {
   const int pbase = (cx * PY + cy) * PZ + cz;
   auto point_offset = [PY, PZ](int s) { return (s & 1) * (PY * PZ) + ((s >> 1) & 1) * PZ + (s >> 2); };
 
+  // Bound on any bin's sum. A tetrahedron's increment over one bin is at most de times its largest
+  // point DOS, 3 V_T / (V_G E41) = 12 V / E41, and all its increments add up to 4 V; index 0 collects
+  // everything below the grid, so a tetrahedron reaching below the first energy counts 4 V. Times bmax.
+  float bound = 0.0f;
+  if (valid) {
+#pragma unroll 1
+    for (int t = 0; t < 6; ++t) {
+      const uint32_t slots = tet_slots(t);
+      float lo = __builtin_huge_valf(), hi = -__builtin_huge_valf();
+      bool fin = true;
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        const float e = s_eps[pbase + point_offset((slots >> (4 * l)) & 7)];
+        fin = fin && __builtin_isfinite(e);
+        lo = fminf(lo, e);
+        hi = fmaxf(hi, e);
+      }
+      if (!fin) continue;
+      const float pos = (lo - a.e0) * a.inv_de - a.joff;  // grid position of E1
+      bound += pos <= 1.0f ? 4.0f : fminf(4.0f, 12.0f * a.de * rcp(hi - lo));
+    }
+  }
+  bound = wave_sum(bound);
+  __syncthreads();  // every lane has read s_red
+  if ((tid & 63) == 0) s_red[tid >> 6] = bound;
+  __syncthreads();
+  float B = 0.0f;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) B += s_red[i];
+  B *= a.V * bmax;
+  if (!(B > 0.0f)) return;  // no finite tetrahedron (uniform across the block)
+
   const bool packed = bmin >= 0.0f;  // uniform across the block
   const int rows = packed ? NPAIR : NORB;
   const int RS = packed ? RSP : RSW;
@@ -152,8 +188,6 @@ __global__ __launch_bounds__(NT) void nos_kernel(NosArgs a) {
   const int cpl = span <= (RS >> 3) ? 3 : span <= (RS >> 2) ? 2 : span <= (RS >> 1) ? 1 : 0;  // log2 of copies
   const int CP = 1 << cpl;
   const int LC = RS >> cpl;
-  // Bound on any bin: 4 V bmax for each of the tile's 6 NT tetrahedra.
-  const float B = 24.0f * (float)NT * a.V * bmax;
   int bexp;
   frexpf(fminf(B, 3.0e38f), &bexp);
   const int sexp = min((packed ? 30 : 62) - bexp, 126);

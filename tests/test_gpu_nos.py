@@ -126,6 +126,25 @@ def test_signed_weights(torch_dev, oracle_lib):
     assert _err(gn, rn) <= TOL and _err(gb, rb) <= TOL
 
 
+@pytest.mark.parametrize("signed", [False, True])
+def test_many_energies_several_histogram_passes(torch_dev, oracle_lib, signed):
+    """16 orbitals and 3000 energies: a tile-band's index range exceeds one LDS histogram, so the
+    kernel makes several passes and each starts one index early to know the weights there."""
+    torch, dev = torch_dev
+    grid, norb, ne = (5, 7, 3), 16, 3000
+    eps, w = synth.band_structure(norb, 12, grid)
+    if signed:
+        w = (w - np.float32(0.05)).astype(np.float32)
+    e0, de = _grid_inside(eps, ne, 0.05, 0.95)
+    print(f"[case] nos {grid} norb={norb} ne={ne} signed={signed}", flush=True)
+    rn = oracle_lib.nos(eps, w, grid, e0, de, ne)
+    rb = oracle_lib.dos_binned(eps, w, grid, e0, de, ne)
+    gn, gb = _run(torch, dev, eps, w, grid, e0, de, ne)
+    en, eb = _err(gn, rn), _err(gb, rb)
+    print(f"[case] err nos {en:.3e} binned {eb:.3e}", flush=True)
+    assert en <= TOL and eb <= TOL
+
+
 def test_grid_outside_the_bands(torch_dev, oracle_lib):
     torch, dev = torch_dev
     grid, norb, ne = (7, 8, 9), 4, 50
