@@ -233,10 +233,13 @@ def summarize_profiles(kt_dir, fetch_dir=None, write_dir=None, copy_fetch_dir=No
             rd, wt = fe[k] * 1024 * f_fetch, wr[k] * 1024 * f_write
             lines.append(f"| `{k[:90]}` | {fe[k]:.0f} | {wr[k]:.0f} | {rd / 1e6:.2f} | {wt / 1e6:.2f} |")
             for short in ("dos_forward_kernel", "dos_backward_kernel", "nos_kernel"):
-                if short in k:
+                if short in k:  # instantiations launched by one call add up
                     sha = (source_shas or {}).get(short) or kernel_source_hash(short)
-                    traffic[short] = {"source_sha": sha, "bytes_per_launch": rd + wt,
-                                      "read_bytes": rd, "write_bytes": wt}
+                    rec = traffic.setdefault(short, {"source_sha": sha, "bytes_per_launch": 0.0,
+                                                     "read_bytes": 0.0, "write_bytes": 0.0})
+                    rec["bytes_per_launch"] += rd + wt
+                    rec["read_bytes"] += rd
+                    rec["write_bytes"] += wt
     if out_json and traffic:
         try:  # keep the records of kernels this run did not profile
             with open(out_json) as f:
@@ -389,8 +392,12 @@ def bench_nos(args, torch, tetra, dev):
     if args.tiles:  # every launch of the run with the given shape (for profiles)
         tile, sweep = int(args.tiles.split(",")[0]), None
     else:
-        sweep = {t: _time_events(torch, lambda t=t: tetra.dos_binned(eps, w, grid, e0, de, ne, out=out_b, tile=t),
-                                 3, 1) for t in range(len(tetra.TILE_SHAPES))}
+        sweep = {}
+        for r in range(2):  # best of two sweeps in opposite orders
+            for t in (range(6) if r == 0 else range(5, -1, -1)):
+                ms_t = _time_events(torch, lambda t=t: tetra.dos_binned(eps, w, grid, e0, de, ne, out=out_b, tile=t),
+                                    3, 1)
+                sweep[t] = min(sweep.get(t, float("inf")), ms_t)
         tile = min(sweep, key=sweep.get)
     stream = torch.cuda.current_stream(dev)
     runs = {"nos": lambda: tetra.nos_forward(eps, w, grid, e0, de, ne, out=out_n, tile=tile),
@@ -425,7 +432,7 @@ def bench_nos(args, torch, tetra, dev):
                    "tile": list(tetra.TILE_SHAPES[tile])},
         "ms": ms,
         "binned_updates_per_s": dense / (ms["binned"] * 1e-3),
-        "roofline": {"bound": "alu", "kernel": "nos_kernel (bin averages; events include the zero fill)",
+        "roofline": {"bound": "alu", "kernel": "nos_kernel, both precisions (bin averages; events include the zero fill)",
                      "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": load_traffic("nos_kernel"),
                      "algorithmic_flops_per_launch": flops, "avg_launch_ms": ms["binned"]},

@@ -13,7 +13,9 @@
  * energies of each tetrahedron-band sorted ascending, and E_j = e0 + j*de (an equidistant energy
  * grid, Sec. IV.A). The inputs follow the paper's statement of the problem: band energies E_n(k)
  * and orbital weights b_mn(k) = |a^m_n(k)|^2 (eq. matrixelements) on the k-grid, stored as
- * linearised arrays (Sec. III.B).
+ * linearised arrays (Sec. III.B), or the amplitudes a^m_n(k) themselves. Besides the DOS and its
+ * adjoint: the orbital-resolved number of states with the integrated weights w_{n,l} (eq.
+ * BZintegral) and the bin-averaged DOS derived from it.
  *
  * Conventions shared by every entry point:
  *  - k-grid: n1 x n2 x n3 points, periodic, k = (i1*n2 + i2)*n3 + i3 (i3 fastest). Every grid point

@@ -44,6 +44,7 @@ struct NosArgs {
   int shift;   // grid index j is written to output row j - shift (rows below 0 are dropped)
   int nout;    // output rows
   float e0, de, inv_de, joff, V;
+  double Vd;  // V_T / (4 V_G) in FP64
   double out_scale;  // applied to every flushed sum (1, or 1/de for bin averages)
   int TX, TY, TZ;
   int t1, t2, t3;
@@ -69,7 +70,11 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-template <int NORB, typename WT>
+// FP64 = false: the workgroups whose widest tetrahedron spans at most 64 energy steps, with FP32
+// integrated weights; FP64 = true: the others, with FP64 weights. Both instantiations run over every
+// unit, take the same decision from the same energies and leave early on the units of the other, so
+// each keeps its own register budget (and occupancy).
+template <int NORB, typename WT, bool FP64>
 __global__ __launch_bounds__(NT) void nos_kernel(NosArgs a) {
   constexpr int NPAIR = (NORB + 1) / 2;
   constexpr int RSP = (HCAP / NPAIR - 1) | 1, RSW = (HCAP / NORB - 1) | 1;
@@ -96,7 +101,8 @@ __global__ __launch_bounds__(NT) void nos_kernel(NosArgs a) {
   const WT* w_n = static_cast<const WT*>(a.w) + (int64_t)band * NORB * nk;
   const float wscale = a.w_scale ? a.w_scale[band] : 1.0f;
 
-  float lmin = __builtin_huge_valf(), lmax = -__builtin_huge_valf(), lbmax = 0.0f, lbmin = 0.0f;
+  // Stage the tile's energies; the orbital weights only once the unit is known to be ours.
+  float lmin = __builtin_huge_valf(), lmax = -__builtin_huge_valf();
   for (int p = tid; p < NP; p += NT) {
     const int pz = p % PZ, py = (p / PZ) % PY, px = p / (PZ * PY);
     const int64_t k = ((int64_t)wrap(x0 + px, a.n1) * a.n2 + wrap(y0 + py, a.n2)) * a.n3 + wrap(z0 + pz, a.n3);
@@ -106,34 +112,21 @@ __global__ __launch_bounds__(NT) void nos_kernel(NosArgs a) {
       lmin = fminf(lmin, e);
       lmax = fmaxf(lmax, e);
     }
-#pragma unroll
-    for (int m = 0; m < NORB; ++m) {
-      const float v = weight_value(w_n[(int64_t)m * nk + k], wscale);
-      s_w[p * NORB + m] = v;
-      lbmax = fmaxf(lbmax, fabsf(v));
-      lbmin = fminf(lbmin, v);
-    }
   }
   lmin = wave_min(lmin);
   lmax = wave_max(lmax);
-  lbmax = wave_max(lbmax);
-  lbmin = wave_min(lbmin);
   if ((tid & 63) == 0) {
     s_red[tid >> 6] = lmin;
     s_red[(NT / 64) + (tid >> 6)] = lmax;
-    s_red[2 * (NT / 64) + (tid >> 6)] = lbmax;
-    s_red[3 * (NT / 64) + (tid >> 6)] = lbmin;
   }
   __syncthreads();
-  float emin = s_red[0], emax = s_red[NT / 64], bmax = s_red[2 * (NT / 64)], bmin = s_red[3 * (NT / 64)];
+  float emin = s_red[0], emax = s_red[NT / 64];
 #pragma unroll
   for (int i = 1; i < NT / 64; ++i) {
     emin = fminf(emin, s_red[i]);
     emax = fmaxf(emax, s_red[NT / 64 + i]);
-    bmax = fmaxf(bmax, s_red[2 * (NT / 64) + i]);
-    bmin = fminf(bmin, s_red[3 * (NT / 64) + i]);
   }
-  if (!(emin <= emax) || !(bmax > 0.0f)) return;  // nothing to add (uniform across the block)
+  if (!(emin <= emax)) return;  // no finite energy (uniform across the block)
   // Grid indices this tile-band can touch: from the first E_j above its lowest energy to the first
   // E_j at or above its highest, one index of margin for the FP32 estimates.
   const float big = 3.0e7f;
@@ -151,8 +144,9 @@ __global__ __launch_bounds__(NT) void nos_kernel(NosArgs a) {
 
   // Bound on any bin's sum. A tetrahedron's increment over one bin is at most de times its largest
   // point DOS, 3 V_T / (V_G E41) = 12 V / E41, and all its increments add up to 4 V; index 0 collects
-  // everything below the grid, so a tetrahedron reaching below the first energy counts 4 V. Times bmax.
-  float bound = 0.0f;
+  // everything below the grid, so a tetrahedron reaching below the first energy counts 4 V (times
+  // bmax below). The widest tetrahedron in units of de picks the precision.
+  float bound = 0.0f, wide = 0.0f;
   if (valid) {
 #pragma unroll 1
     for (int t = 0; t < 6; ++t) {
@@ -169,17 +163,55 @@ __global__ __launch_bounds__(NT) void nos_kernel(NosArgs a) {
       if (!fin) continue;
       const float pos = (lo - a.e0) * a.inv_de - a.joff;  // grid position of E1
       bound += pos <= 1.0f ? 4.0f : fminf(4.0f, 12.0f * a.de * rcp(hi - lo));
+      wide = fmaxf(wide, (hi - lo) * a.inv_de);
     }
   }
   bound = wave_sum(bound);
+  wide = wave_max(wide);
   __syncthreads();  // every lane has read s_red
-  if ((tid & 63) == 0) s_red[tid >> 6] = bound;
+  if ((tid & 63) == 0) {
+    s_red[tid >> 6] = bound;
+    s_red[(NT / 64) + (tid >> 6)] = wide;
+  }
   __syncthreads();
   float B = 0.0f;
 #pragma unroll
-  for (int i = 0; i < NT / 64; ++i) B += s_red[i];
+  for (int i = 0; i < NT / 64; ++i) {
+    B += s_red[i];
+    wide = fmaxf(wide, s_red[NT / 64 + i]);
+  }
+  // FP32 increments lose about 1e-7 E41/de of their value to cancellation: FP64 beyond E41 = 64 de.
+  if ((wide > 64.0f) != FP64) return;  // the other instantiation's unit (uniform across the block)
+  if (!(B > 0.0f)) return;             // no finite tetrahedron
+
+  float lbmax = 0.0f, lbmin = 0.0f;
+  for (int p = tid; p < NP; p += NT) {
+    const int pz = p % PZ, py = (p / PZ) % PY, px = p / (PZ * PY);
+    const int64_t k = ((int64_t)wrap(x0 + px, a.n1) * a.n2 + wrap(y0 + py, a.n2)) * a.n3 + wrap(z0 + pz, a.n3);
+#pragma unroll
+    for (int m = 0; m < NORB; ++m) {
+      const float v = weight_value(w_n[(int64_t)m * nk + k], wscale);
+      s_w[p * NORB + m] = v;
+      lbmax = fmaxf(lbmax, fabsf(v));
+      lbmin = fminf(lbmin, v);
+    }
+  }
+  lbmax = wave_max(lbmax);
+  lbmin = wave_min(lbmin);
+  __syncthreads();  // every lane has read s_red
+  if ((tid & 63) == 0) {
+    s_red[tid >> 6] = lbmax;
+    s_red[(NT / 64) + (tid >> 6)] = lbmin;
+  }
+  __syncthreads();
+  float bmax = s_red[0], bmin = s_red[NT / 64];
+#pragma unroll
+  for (int i = 1; i < NT / 64; ++i) {
+    bmax = fmaxf(bmax, s_red[i]);
+    bmin = fminf(bmin, s_red[NT / 64 + i]);
+  }
+  if (!(bmax > 0.0f)) return;  // all weights zero: nothing to add
   B *= a.V * bmax;
-  if (!(B > 0.0f)) return;  // no finite tetrahedron (uniform across the block)
 
   const bool packed = bmin >= 0.0f;  // uniform across the block
   const int rows = packed ? NPAIR : NORB;
@@ -220,6 +252,7 @@ __global__ __launch_bounds__(NT) void nos_kernel(NosArgs a) {
         }
         if (!finite4(e[0], e[1], e[2], e[3])) continue;
         sort4(e, pt);
+        // FP32 frames for the exact index windows
         TetSetup cs = tet_setup(e, a.e0, V);
         shift_frames(cs, a.joff * a.de);
         int ja, js;
@@ -266,30 +299,60 @@ __global__ __launch_bounds__(NT) void nos_kernel(NosArgs a) {
             }
           }
         };
-        float coef[4][5];
-        if (jB > jA) corner_nos_B_coeffs(cs, V, coef);
-        float prev[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        for (int j = jstart; j <= jend; ++j) {
-          float cur[4];
-          if (j >= js0) {
+        // w_l is non-decreasing in E: a negative difference is rounding
+        if constexpr (FP64) {
+          const NosSetup ns = nos_setup(e, a.e0, a.joff, a.de, a.Vd);
+          double coef[4][5];
+          if (jB > jA) corner_nos_B_coeffs(ns, a.Vd, coef);
+          const double dde = (double)a.de;
+          double prev[4] = {0.0, 0.0, 0.0, 0.0};
+          for (int j = jstart; j <= jend; ++j) {
+            double cur[4];
+            const double jd = (double)j;
+            if (j >= js0) {
 #pragma unroll
-            for (int l = 0; l < 4; ++l) cur[l] = V;
-          } else if (j <= jA) {
-            corner_nos_A(cs, local_x(cs, j, a.de), cur);
-          } else if (j <= jB) {
-            corner_nos_B_poly(coef, local_z(cs, j, a.de), cur);
-          } else {
-            corner_nos_C(cs, V, local_y(cs, j, a.de), cur);
+              for (int l = 0; l < 4; ++l) cur[l] = a.Vd;
+            } else if (j <= jA) {
+              corner_nos_A(ns, __builtin_fma(jd, dde, ns.x0), cur);
+            } else if (j <= jB) {
+              corner_nos_B_poly(coef, __builtin_fma(jd, dde, ns.z0), cur);
+            } else {
+              corner_nos_C(ns, a.Vd, __builtin_fma(-jd, dde, ns.y0), cur);
+            }
+            if (j >= c0) {
+              float inc[4];
+#pragma unroll
+              for (int l = 0; l < 4; ++l) inc[l] = (float)fmax(cur[l] - prev[l], 0.0);
+              deposit(j, inc);
+            }
+#pragma unroll
+            for (int l = 0; l < 4; ++l) prev[l] = cur[l];
           }
-          if (j >= c0) {
-            float inc[4];
-            // w_l is non-decreasing in E; a negative difference is rounding
+        } else {
+          float coef[4][5];
+          if (jB > jA) corner_nos_B_coeffs(cs, V, coef);
+          float prev[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+          for (int j = jstart; j <= jend; ++j) {
+            float cur[4];
+            if (j >= js0) {
 #pragma unroll
-            for (int l = 0; l < 4; ++l) inc[l] = fmaxf(cur[l] - prev[l], 0.0f);
-            deposit(j, inc);
+              for (int l = 0; l < 4; ++l) cur[l] = V;
+            } else if (j <= jA) {
+              corner_nos_A(cs, local_x(cs, j, a.de), cur);
+            } else if (j <= jB) {
+              corner_nos_B_poly(coef, local_z(cs, j, a.de), cur);
+            } else {
+              corner_nos_C(cs, V, local_y(cs, j, a.de), cur);
+            }
+            if (j >= c0) {
+              float inc[4];
+#pragma unroll
+              for (int l = 0; l < 4; ++l) inc[l] = fmaxf(cur[l] - prev[l], 0.0f);
+              deposit(j, inc);
+            }
+#pragma unroll
+            for (int l = 0; l < 4; ++l) prev[l] = cur[l];
           }
-#pragma unroll
-          for (int l = 0; l < 4; ++l) prev[l] = cur[l];
         }
       }
     }
@@ -338,15 +401,21 @@ __global__ __launch_bounds__(256) void column_scan_kernel(float* p, int n, int n
   }
 }
 
+template <int NORB, bool FP64>
+hipError_t launch_nos_prec(const NosArgs& a, int grid, hipStream_t s) {
+  if (a.wtype == TETRA_W_F16)
+    hipLaunchKernelGGL((nos_kernel<NORB, _Float16, FP64>), dim3(grid), dim3(NT), 0, s, a);
+  else if (a.wtype == TETRA_W_C32)
+    hipLaunchKernelGGL((nos_kernel<NORB, float2, FP64>), dim3(grid), dim3(NT), 0, s, a);
+  else
+    hipLaunchKernelGGL((nos_kernel<NORB, float, FP64>), dim3(grid), dim3(NT), 0, s, a);
+  return hipGetLastError();
+}
+
 template <int NORB>
 hipError_t launch_nos(const NosArgs& a, int grid, hipStream_t s) {
-  if (a.wtype == TETRA_W_F16)
-    hipLaunchKernelGGL((nos_kernel<NORB, _Float16>), dim3(grid), dim3(NT), 0, s, a);
-  else if (a.wtype == TETRA_W_C32)
-    hipLaunchKernelGGL((nos_kernel<NORB, float2>), dim3(grid), dim3(NT), 0, s, a);
-  else
-    hipLaunchKernelGGL((nos_kernel<NORB, float>), dim3(grid), dim3(NT), 0, s, a);
-  return hipGetLastError();
+  const hipError_t e = launch_nos_prec<NORB, false>(a, grid, s);
+  return e != hipSuccess ? e : launch_nos_prec<NORB, true>(a, grid, s);
 }
 
 }  // namespace
@@ -365,7 +434,8 @@ hipError_t nos(const tetra_desc& d, const float* eps, const void* w, int wtype, 
   a.e0 = d.e0;
   a.de = d.de;
   a.inv_de = 1.0f / d.de;
-  a.V = (float)(1.0 / (24.0 * (double)d.n1 * d.n2 * d.n3));  // V_T / (4 V_G)
+  a.Vd = 1.0 / (24.0 * (double)d.n1 * d.n2 * d.n3);  // V_T / (4 V_G)
+  a.V = (float)a.Vd;
   a.nout = d.ne;
   if (binned) {  // increments between the midpoints E_j -+ de/2: ne + 1 grid indices, the first dropped
     a.ng = d.ne + 1;

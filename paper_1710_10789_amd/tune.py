@@ -1,8 +1,8 @@
 """Autotuner for the tile shape of the forward and adjoint kernels.
 
 For a problem class (GPU name, kernel, weight dtype, bands, orbitals, k-point bucket, energy-count
-bucket) every tile shape of ``TILE_SHAPES`` is timed on the current stream with HIP events, and the
-fastest is kept in a JSON cache (``$TETRA_TUNE_CACHE``, default ``~/.cache/tetra_tune.json``).
+bucket) every tile shape of ``TILE_SHAPES`` is timed on the current stream with HIP events (the best
+of two sweeps in opposite orders), and the fastest is kept in a JSON cache (``$TETRA_TUNE_CACHE``, default ``~/.cache/tetra_tune.json``).
 Lookups of an untuned class fall back to the default shape 0.
 """
 from __future__ import annotations
@@ -66,6 +66,18 @@ def _time(fn, reps):
     return start.elapsed_time(stop) / reps
 
 
+def _sweep(make, reps, rounds):
+    """Best time per tile shape over ``rounds`` sweeps, alternating the order of the shapes, so that
+    clock ramp-up and cache state do not favour the shapes timed last."""
+    n = len(TILE_SHAPES)
+    best = [float("inf")] * n
+    for r in range(rounds):
+        order = range(n) if r % 2 == 0 else range(n - 1, -1, -1)
+        for t in order:
+            best[t] = min(best[t], _time(make(t), reps))
+    return best
+
+
 def _record(key, times):
     best = min(range(len(times)), key=lambda i: times[i])
     _load()[key] = {"tile": best, "shape": list(TILE_SHAPES[best]), "ms": times}
@@ -73,25 +85,24 @@ def _record(key, times):
     return best
 
 
-def tune_forward(eps, w, grid, e0, de, ne, w_scale=None, reps: int = 3):
+def tune_forward(eps, w, grid, e0, de, ne, w_scale=None, reps: int = 3, rounds: int = 2):
     """Time every tile shape of the forward kernel on this problem; returns (best, [ms per shape])."""
     import torch
 
     out = torch.empty((int(ne), w.shape[1]), dtype=torch.float32, device=eps.device)
-    times = [_time(lambda t=t: dos_forward(eps, w, grid, e0, de, ne, w_scale=w_scale, out=out, tile=t), reps)
-             for t in range(len(TILE_SHAPES))]
+    times = _sweep(lambda t: (lambda: dos_forward(eps, w, grid, e0, de, ne, w_scale=w_scale, out=out, tile=t)),
+                   reps, rounds)
     return _record(problem_key("forward", eps, w, grid, ne), times), times
 
 
-def tune_backward(eps, w, grid, e0, de, grad_dos, w_scale=None, reps: int = 3):
+def tune_backward(eps, w, grid, e0, de, grad_dos, w_scale=None, reps: int = 3, rounds: int = 2):
     """Time every tile shape of the adjoint kernel on this problem; returns (best, [ms per shape])."""
     import torch
 
     ge = torch.empty_like(eps)
-    gw = torch.empty(w.shape, dtype=torch.float32, device=eps.device)
-    times = [_time(lambda t=t: dos_backward(eps, w, grid, e0, de, grad_dos, w_scale=w_scale, grad_eps=ge,
-                                            grad_w=gw, tile=t), reps)
-             for t in range(len(TILE_SHAPES))]
+    gw = torch.empty(w.shape, dtype=torch.complex64 if w.is_complex() else torch.float32, device=eps.device)
+    times = _sweep(lambda t: (lambda: dos_backward(eps, w, grid, e0, de, grad_dos, w_scale=w_scale, grad_eps=ge,
+                                                   grad_w=gw, tile=t)), reps, rounds)
     return _record(problem_key("backward", eps, w, grid, grad_dos.shape[0]), times), times
 
 

@@ -134,13 +134,15 @@ int main(int argc, char** argv) {
     std::printf("%s %ld %.6e %.6e %.6e %.6e\n", names[k], ranges[k], werr[k], eerr[k][0], eerr[k][1], berr[k]);
 
   // Integrated weights (number of states) as the kernel forms them: the exact steps ja (first E_j > E1)
-  // and js (first E_j >= E4) of step_window, the case split of the window [ja, js), the case
-  // polynomials, and V from js on, on the grid E_j = e0 + (j + joff) de for joff = 0 and -1/2 (the
-  // bin midpoints). Compared with the oracle's w_l(E_j) for every j from ja - 2 to js + 1, relative
-  // to V; a step index that disagrees with the FP64 comparison by more than FP32 rounding is counted.
+  // and js (first E_j >= E4) of step_window on the FP32 frames, the case split of the window [ja, js),
+  // the case polynomials in FP64 and in FP32, and V from js on, on the grid E_j = e0 + (j + joff) de for joff = 0
+  // and -1/2 (the bin midpoints). Compared with the oracle's w_l(E_j) for every j from ja - 2 to
+  // js + 1, relative to V; a step index that disagrees with the FP64 comparison by more than FP32
+  // rounding is counted. Then the increments w_l(E_j) - w_l(E_{j-1}) on grids 1e3 and 1e5 times finer
+  // than the tetrahedron, relative to the largest increment of the tetrahedron.
   for (int half = 0; half < 2; ++half) {
     const float joff = half ? -0.5f : 0.0f;
-    double nerr = 0.0;
+    double nerr = 0.0, nerr32 = 0.0;
     long npts = 0, nbad = 0;
     for (int it = 0; it < n; ++it) {
       float e[4];
@@ -153,6 +155,7 @@ int main(int argc, char** argv) {
       const double ed[4] = {e[0], e[1], e[2], e[3]};
       TetSetup cs = tet_setup(e, e0, V);
       shift_frames(cs, joff * de);
+      const NosSetup ns = nos_setup(e, e0, joff, de, (double)V);
       int ja, js;
       step_window(cs, e[0], e[3], e0, joff, de, 1.0f / de, ja, js);
       auto Ej = [&](int j) { return (double)e0 + ((double)j + (double)joff) * (double)de; };
@@ -168,28 +171,84 @@ int main(int argc, char** argv) {
       const int lo = std::min(ja, js), jlast = js - 1;
       int jA = lo - 1, jB = lo - 1;
       if (jlast >= lo) case_split(cs, de, 1.0f / de, lo, jlast, jA, jB);
-      float coef[4][5];
-      corner_nos_B_coeffs(cs, V, coef);
+      double coef[4][5];
+      corner_nos_B_coeffs(ns, (double)V, coef);
+      float coef32[4][5];
+      corner_nos_B_coeffs(cs, V, coef32);
       for (int j = lo - 2; j <= js + 1; ++j) {
-        float w[4];
+        double w[4];
+        float w32[4];
         if (j < lo) {
-          for (int l = 0; l < 4; ++l) w[l] = 0.0f;
+          for (int l = 0; l < 4; ++l) w[l] = w32[l] = 0.0f;
         } else if (j >= js) {
-          for (int l = 0; l < 4; ++l) w[l] = V;
+          for (int l = 0; l < 4; ++l) w[l] = w32[l] = V;
         } else if (j <= jA) {
-          corner_nos_A(cs, local_x(cs, j, de), w);
+          corner_nos_A(ns, std::fma((double)j, (double)de, ns.x0), w);
+          corner_nos_A(cs, local_x(cs, j, de), w32);
         } else if (j <= jB) {
-          corner_nos_B_poly(coef, local_z(cs, j, de), w);
+          corner_nos_B_poly(coef, std::fma((double)j, (double)de, ns.z0), w);
+          corner_nos_B_poly(coef32, local_z(cs, j, de), w32);
         } else {
-          corner_nos_C(cs, V, local_y(cs, j, de), w);
+          corner_nos_C(ns, (double)V, std::fma(-(double)j, (double)de, ns.y0), w);
+          corner_nos_C(cs, V, local_y(cs, j, de), w32);
         }
         double wr[4], gr[4];
         tetra_oracle_corner_weights(ed, Ej(j), 4.0 * V, wr, gr);
-        for (int l = 0; l < 4; ++l) nerr = std::fmax(nerr, std::isfinite(w[l]) ? std::fabs(w[l] - wr[l]) / V : INFINITY);
+        for (int l = 0; l < 4; ++l) {
+          nerr = std::fmax(nerr, std::isfinite(w[l]) ? std::fabs(w[l] - wr[l]) / V : INFINITY);
+          nerr32 = std::fmax(nerr32, std::isfinite(w32[l]) ? std::fabs(w32[l] - wr[l]) / V : INFINITY);
+        }
         ++npts;
       }
     }
     std::printf("%s %ld %.6e %ld\n", half ? "nos_half" : "nos", npts, nerr, nbad);
+    std::printf("%s %ld %.6e %ld\n", half ? "nos32_half" : "nos32", npts, nerr32, nbad);
+  }
+  for (int fine = 0; fine < 2; ++fine) {
+    const double ratio = fine ? 1.0e5 : 1.0e3;  // E41 / de
+    double ierr = 0.0;
+    long ninc = 0;
+    for (int it = 0; it < n / 10; ++it) {
+      float e[4];
+      for (int l = 0; l < 4; ++l) e[l] = U(rng);
+      int p[4] = {0, 1, 2, 3};
+      sort4(e, p);
+      const double ed[4] = {e[0], e[1], e[2], e[3]};
+      if (!(ed[3] - ed[0] > 1e-2)) continue;
+      const float dg = (float)((ed[3] - ed[0]) / ratio), g0 = -1.5f;
+      const NosSetup ns = nos_setup(e, g0, 0.0f, dg, (double)V);
+      double coef[4][5];
+      corner_nos_B_coeffs(ns, (double)V, coef);
+      // three sample bins per case, away from the case boundaries (the kernel splits the window at them)
+      const double bnd[4] = {ed[0], ed[1], ed[2], ed[3]};
+      double incmax = 0.0, emax = 0.0;
+      for (int cse = 0; cse < 3; ++cse) {
+        if (!(bnd[cse + 1] - bnd[cse] > 10.0 * dg)) continue;
+        for (int q = 1; q <= 3; ++q) {
+          const double Emid = bnd[cse] + (bnd[cse + 1] - bnd[cse]) * q / 4.0;
+          const int j = (int)std::floor((Emid - g0) / dg);
+          double w1[4], w0[4];
+          for (int side = 0; side < 2; ++side) {
+            double* w = side ? w1 : w0;
+            const double jd = (double)(j - 1 + side);
+            if (cse == 0) corner_nos_A(ns, std::fma(jd, (double)dg, ns.x0), w);
+            else if (cse == 1) corner_nos_B_poly(coef, std::fma(jd, (double)dg, ns.z0), w);
+            else corner_nos_C(ns, (double)V, std::fma(-jd, (double)dg, ns.y0), w);
+          }
+          double r1[4], r0[4], gr[4];
+          tetra_oracle_corner_weights(ed, (double)g0 + (double)j * dg, 4.0 * V, r1, gr);
+          tetra_oracle_corner_weights(ed, (double)g0 + (double)(j - 1) * dg, 4.0 * V, r0, gr);
+          for (int l = 0; l < 4; ++l) {
+            const float inc = (float)std::fmax(w1[l] - w0[l], 0.0);
+            incmax = std::fmax(incmax, r1[l] - r0[l]);
+            emax = std::fmax(emax, std::fabs((double)inc - (r1[l] - r0[l])));
+          }
+          ++ninc;
+        }
+      }
+      if (incmax > 0.0) ierr = std::fmax(ierr, emax / incmax);
+    }
+    std::printf("inc%s %ld %.6e\n", fine ? "_1e5" : "_1e3", ninc, ierr);
   }
   return 0;
 }

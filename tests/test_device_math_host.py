@@ -8,8 +8,10 @@ No GPU needed; the harness is test code only.
 
 Bounds (FP32 arithmetic against FP64): corner weights within 1e-5 of the tetrahedron's largest
 weight; a case range's energy gradient within 5e-4 of the sum of its per-energy |derivatives|, and its
-weight gradient within 1e-5 of sum_j |G| |g|; integrated weights within 1e-5 of V_T/(4 V_G) (a sign or
-index mistake in any term gives O(1))."""
+weight gradient within 1e-5 of sum_j |G| |g|; integrated weights within 1e-9 (FP64) and 1e-5 (FP32)
+of V_T/(4 V_G),
+and their increments over bins 1e3 and 1e5 times narrower than the tetrahedron within 1e-6 of the
+tetrahedron's largest increment (a sign or index mistake in any term gives O(1))."""
 import os
 import shutil
 import subprocess
@@ -48,11 +50,21 @@ def test_corner_weights_and_moment_adjoint_against_oracle(harness):
         parts = line.split()
         if len(parts) == 4:
             nos[parts[0]] = (int(parts[1]), float(parts[2]), int(parts[3]))
-    assert set(nos) == {"nos", "nos_half"}
+    assert set(nos) == {"nos", "nos_half", "nos32", "nos32_half"}
     for grid, (npts, err, bad) in nos.items():
         assert npts > 100000, grid
-        assert err <= 1e-5, (grid, err)  # integrated weights, relative to V_T/(4 V_G)
+        # integrated weights relative to V_T/(4 V_G): FP64 and FP32 evaluation
+        assert err <= (1e-5 if grid.startswith("nos32") else 1e-9), (grid, err)
         assert bad == 0, grid  # number-of-states steps at the right grid indices
+    inc = {}
+    for line in res.stdout.split("\n"):
+        parts = line.split()
+        if len(parts) == 3 and parts[0].startswith("inc_"):
+            inc[parts[0]] = (int(parts[1]), float(parts[2]))
+    assert set(inc) == {"inc_1e3", "inc_1e5"}
+    for grid, (ninc, err) in inc.items():
+        assert ninc > 1000, grid
+        assert err <= 1e-6, (grid, err)  # increments on bins 1e3 and 1e5 times finer than the tetrahedron
     assert set(rows) == {"first", "middle", "third"}
     for case, (n, werr, gen, deg, berr) in rows.items():
         assert n > 1000, case
