@@ -138,7 +138,10 @@ tetra_status tetra_dos_backward(const tetra_desc* d, const float* eps, const voi
  * with w_l = 0 for E_j <= E1 and w_l = V_T/(4 V_G) for E_j >= E4, so nos[j][m] counts the states of
  * orbital m up to E_j per k-point (unit cell). Arguments as for tetra_dos_forward; nos is device
  * float [ne][norb], overwritten. flags: TETRA_TILE(shape) or 0 (TETRA_KAHAN and TETRA_DETERMINISTIC
- * give TETRA_ERR_UNSUPPORTED). Allocates nothing.
+ * give TETRA_ERR_UNSUPPORTED). The kernels add the increments of each tetrahedron-band's weights
+ * between neighbouring grid energies; the weights are evaluated in FP32, or in FP64 on the tiles
+ * where a tetrahedron spans more than 64 energy steps (FP32 increments there would lose about
+ * 1e-7 E41/de of their value to cancellation). Allocates nothing.
  */
 tetra_status tetra_nos_forward(const tetra_desc* d, const float* eps, const void* w, int wtype,
                                const float* w_scale, float* nos, unsigned flags, void* stream);

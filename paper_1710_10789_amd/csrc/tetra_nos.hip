@@ -127,6 +127,8 @@ __global__ __launch_bounds__(NT) void nos_kernel(NosArgs a) {
     emax = fmaxf(emax, s_red[NT / 64 + i]);
   }
   if (!(emin <= emax)) return;  // no finite energy (uniform across the block)
+  // No tetrahedron of the tile spans more than its energy range: the FP32 instantiation's unit.
+  if (FP64 && (emax - emin) * a.inv_de <= 64.0f) return;
   // Grid indices this tile-band can touch: from the first E_j above its lowest energy to the first
   // E_j at or above its highest, one index of margin for the FP32 estimates.
   const float big = 3.0e7f;
