@@ -19,6 +19,10 @@
 // grid indices (two orbitals per 64-bit word when the weights are non-negative; every increment is
 // then non-negative too, w_l being non-decreasing in E). A bin's sum over the tile's tetrahedra is
 // bounded per tetrahedron by bmax min(4 V, 12 V de / E41), which fixes the scale.
+//
+// The weights are evaluated in FP32, or in FP64 on tile-bands where a tetrahedron spans more than 64
+// energy steps (an increment there is a small difference of values up to V, and FP32 would lose
+// about 1e-7 E41/de of it); two instantiations of the kernel share the work by that test.
 
 #include "tetra_internal.h"
 #include "tetra_weights.h"

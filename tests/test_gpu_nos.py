@@ -145,6 +145,59 @@ def test_many_energies_several_histogram_passes(torch_dev, oracle_lib, signed):
     assert en <= TOL and eb <= TOL
 
 
+def test_non_finite_energies_are_skipped(torch_dev, oracle_lib):
+    """A tetrahedron-band with a non-finite corner energy contributes nothing, below or above."""
+    torch, dev = torch_dev
+    grid, norb, ne = (5, 4, 6), 4, 90
+    eps, w = synth.band_structure(norb, 9, grid)
+    eps = eps.copy()
+    eps[0, 3] = np.nan
+    eps[2, 17] = np.inf
+    eps[3, 40] = -np.inf
+    e0, de = _grid_inside(np.nan_to_num(eps, nan=0.0, posinf=0.0, neginf=0.0), ne, 0.2, 0.9)
+    print("[case] nos with non-finite energies", flush=True)
+    rn = oracle_lib.nos(eps, w, grid, e0, de, ne)
+    rb = oracle_lib.dos_binned(eps, w, grid, e0, de, ne)
+    gn, gb = _run(torch, dev, eps, w, grid, e0, de, ne)
+    assert _err(gn, rn) <= TOL and _err(gb, rb) <= TOL
+
+
+def test_graph_capture_replays(torch_dev):
+    """Both entry points allocate nothing and clear their outputs with kernels: one capture, several
+    replays with eager work between them, every replay equal to the eager result."""
+    torch, dev = torch_dev
+    import paper_1710_10789_amd as tetra
+
+    grid, norb, ne = (9, 7, 18), 5, 150
+    eps, w = synth.band_structure(norb, 3, grid)
+    e0, de = _grid_inside(eps, ne, 0.3, 0.8)
+    te, tw = torch.from_numpy(eps).to(dev), torch.from_numpy(w).to(dev)
+    on = torch.empty((ne, norb), device=dev)
+    ob = torch.empty((ne, norb), device=dev)
+    tetra.nos_forward(te, tw, grid, e0, de, ne, out=on)
+    tetra.dos_binned(te, tw, grid, e0, de, ne, out=ob)
+    en, eb = on.clone(), ob.clone()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    print("[case] nos graph capture", flush=True)
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            tetra.nos_forward(te, tw, grid, e0, de, ne, out=on)
+            tetra.dos_binned(te, tw, grid, e0, de, ne, out=ob)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        on.fill_(-1.0)  # eager work between replays
+        ob.fill_(-1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.allclose(on, en, rtol=1e-6, atol=1e-6 * float(en.abs().max())), rep
+        assert torch.allclose(ob, eb, rtol=1e-6, atol=1e-6 * float(eb.abs().max())), rep
+
+
 def test_grid_outside_the_bands(torch_dev, oracle_lib):
     torch, dev = torch_dev
     grid, norb, ne = (7, 8, 9), 4, 50
