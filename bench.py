@@ -654,6 +654,18 @@ def main():
         "avg_launch_ms": t_k * 1e3,
     }
 
+    # LDS-atomic ceiling of the forward: its deposits are U_win * ceil(norb/2) 64-bit LDS atomic adds
+    # (two orbitals per word), timed against the conflict-free rate of the probe kernel
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    p_blocks, p_iters = cus * 40, 1024
+    ms_probe = _time_events(torch, lambda: tetra.probe_lds_atomics(p_blocks, p_iters, device=dev), 5, 2)
+    rate = p_blocks * 256 * 4 * p_iters / (ms_probe * 1e-3)
+    fwd_atomics = uwin * ((norb + 1) // 2)
+    lds_ceiling = {"lane_atomics_per_s": rate, "forward_lane_atomics": fwd_atomics,
+                   "ceiling_ms": fwd_atomics / rate * 1e3, "forward_ms": t_fwd * 1e3,
+                   "frac": (fwd_atomics / rate) / t_fwd,
+                   "probe": f"{p_blocks} workgroups x 256 lanes x {4 * p_iters} conflict-free ds_add_u64"}
+
     out = {
         "metric": "tetra-band-energy updates/s at 64^3 k, 8 bands, 1000 E; fwd+bwd vs plain fwd",
         # dense-equivalent (tetrahedron, band, energy) triples of the workload per second of a step
@@ -688,6 +700,7 @@ def main():
                          "hbm_gbs_algorithmic": b_fwd / t_fwd / 1e9},
         "roofline_bwd": ({"achieved": f_bwd / t_bwd / 1e12, "frac": f_bwd / t_bwd / 1e12 / PEAK_FP32_VALU_TFLOPS,
                           "hbm_gbs_algorithmic": b_bwd / t_bwd / 1e9} if use_bwd else None),
+        "lds_atomic_ceiling": lds_ceiling,
         "kernel_source_sha": {k: kernel_source_hash(k) for k in KERNEL_SOURCES},
         "autotune_ms": {"forward": times_f, "backward": times_b},
     }

@@ -191,6 +191,16 @@ size_t tetra_dos_batched_workspace(const tetra_item* items, int n, int wtype, un
 tetra_status tetra_dos_batched(const tetra_item* items, int n, int wtype, unsigned flags,
                                void* workspace, size_t ws_bytes, void* stream);
 
+/*
+ * Measurement helper, not part of the DOS computation: `blocks` workgroups of 256 lanes, each lane
+ * issuing `iters` x 4 64-bit LDS atomic adds to a word of its own (no two adds of one instruction to
+ * the same address): the best case of the kernels' histogram deposits. Timed on `stream`, it gives
+ * the device's rate of LDS atomics, a ceiling for the deposit-bound part of the forward kernel.
+ *   out      device, uint64 [blocks], overwritten (one checksum per workgroup)
+ * blocks in 1..2^24, iters in 1..2^24. Allocates nothing.
+ */
+tetra_status tetra_probe_lds_atomics(int blocks, int iters, unsigned long long* out, void* stream);
+
 /* Static text for a status code. */
 const char* tetra_status_string(int status);
 

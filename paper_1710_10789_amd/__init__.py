@@ -116,6 +116,8 @@ def lib():
         L.tetra_dos_batched_workspace.restype = ctypes.c_size_t
         L.tetra_dos_batched.argtypes = [ctypes.POINTER(TetraItem), i, i, u, p, ctypes.c_size_t, p]
         L.tetra_dos_batched.restype = i
+        L.tetra_probe_lds_atomics.argtypes = [i, i, p, p]
+        L.tetra_probe_lds_atomics.restype = i
         L.tetra_status_string.argtypes = [i]
         L.tetra_status_string.restype = ctypes.c_char_p
         L.tetra_last_hip_error.argtypes = []
@@ -391,6 +393,19 @@ def dos(eps, w, grid, e0, de, ne, kahan=False, tile=None, backward_tile=None):
     if _FN is None:
         _FN = _autograd_function()
     return _FN.apply(eps, w, tuple(grid), e0, de, ne, kahan, (tile, backward_tile))
+
+
+def probe_lds_atomics(blocks, iters, device=None, out=None):
+    """Measurement helper: launch ``tetra_probe_lds_atomics`` on the current stream (``blocks`` x 256
+    lanes x ``iters`` x 4 conflict-free 64-bit LDS atomic adds); returns the uint64 checksum tensor."""
+    torch = _torch()
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    if out is None:
+        out = torch.empty(int(blocks), dtype=torch.int64, device=dev)
+    _require(out, "out", (int(blocks),), (torch.int64,), dev)
+    _check("tetra_probe_lds_atomics", lib().tetra_probe_lds_atomics(int(blocks), int(iters), out.data_ptr(),
+                                                                     _stream_handle(dev)))
+    return out
 
 
 def from_eigh(evals, evecs, amplitudes=False):

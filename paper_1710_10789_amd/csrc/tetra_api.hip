@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "tetra_internal.h"
+#include "tetra_probe.h"
 
 namespace {
 
@@ -167,6 +168,11 @@ tetra_status tetra_dos_batched(const tetra_item* items, int n, int wtype, unsign
   std::vector<int> shapes(n);
   for (int i = 0; i < n; ++i) shapes[i] = items[i].tile;
   return hip_status(tetra::batched(items, shapes.data(), n, wtype, workspace, (hipStream_t)stream));
+}
+
+tetra_status tetra_probe_lds_atomics(int blocks, int iters, unsigned long long* out, void* stream) {
+  if (!out || blocks < 1 || blocks > (1 << 24) || iters < 1 || iters > (1 << 24)) return TETRA_ERR_ARG;
+  return hip_status(tetra::probe_lds_atomics(blocks, iters, out, (hipStream_t)stream));
 }
 
 const char* tetra_status_string(int status) {

@@ -174,3 +174,10 @@ def test_from_eigh_layouts():
     assert torch.equal(eps, eps2)
     assert torch.allclose(a.abs() ** 2, w, atol=1e-6)
     assert torch.allclose(a[1, 2, 4].to(torch.complex128), vec[4, 2, 1], atol=1e-6)
+
+
+def test_probe_rejects_bad_arguments(L):
+    assert L.tetra_probe_lds_atomics(0, 10, FAKE, None) == -1
+    assert L.tetra_probe_lds_atomics(4, 0, FAKE, None) == -1
+    assert L.tetra_probe_lds_atomics(4, 10, None, None) == -1
+    assert L.tetra_probe_lds_atomics((1 << 24) + 1, 10, FAKE, None) == -1
