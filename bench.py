@@ -634,6 +634,7 @@ def main():
     fwd_ms = np.array([e[0].elapsed_time(e[1]) for e in events])
     bwd_ms = np.array([e[1].elapsed_time(e[2]) for e in events]) if use_bwd else np.zeros(args.steps)
     ms_per_step = wall * 1e3 / args.steps
+    step_ms = fwd_ms + bwd_ms
     t_fwd = float(fwd_ms.mean()) * 1e-3
     t_bwd = float(bwd_ms.mean()) * 1e-3
 
@@ -691,6 +692,11 @@ def main():
         },
         "fwd_ms": t_fwd * 1e3,
         "bwd_ms": t_bwd * 1e3 if use_bwd else None,
+        # per-step event times (forward + backward): median, minimum, and the paper's statistic
+        # (Sec. IV.A: seven runs, mean of the five shortest) over the first seven timed steps
+        "step_event_ms": {"mean": float(step_ms.mean()), "median": float(np.median(step_ms)),
+                          "min": float(step_ms.min()),
+                          "mean_5_shortest_of_7": float(np.sort(step_ms[:7])[:5].mean()) if len(step_ms) >= 7 else None},
         "fwd_updates_per_s": dense / t_fwd,
         "fwdbwd_updates_per_s": dense / (t_fwd + t_bwd) if use_bwd else None,
         "fwdbwd_over_fwd": (dense / (t_fwd + t_bwd)) / (dense / t_fwd) if use_bwd else None,
