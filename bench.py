@@ -41,7 +41,9 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 KERNEL_SOURCES = {
     "dos_forward_kernel": ("tetra_forward.hip", "tetra_device.h", "tetra_internal.h", "tetra_weights.h"),
-    "dos_backward_kernel": ("tetra_backward.hip", "tetra_device.h", "tetra_internal.h", "tetra_weights.h"),
+    # the adjoint pass: dos_backward_kernel and its gather pass, both in tetra_backward.hip
+    "dos_backward_kernel": ("tetra_backward.hip", "tetra_device.h", "tetra_faces.h", "tetra_internal.h",
+                            "tetra_weights.h"),
     "nos_kernel": ("tetra_nos.hip", "tetra_nos_device.h", "tetra_device.h", "tetra_internal.h", "tetra_weights.h"),
 }
 
@@ -240,8 +242,9 @@ def summarize_profiles(kt_dir, fetch_dir=None, write_dir=None, copy_fetch_dir=No
                 continue
             rd, wt = fe[k] * 1024 * f_fetch, wr[k] * 1024 * f_write
             lines.append(f"| `{k[:90]}` | {fe[k]:.0f} | {wr[k]:.0f} | {rd / 1e6:.2f} | {wt / 1e6:.2f} |")
-            for short in ("dos_forward_kernel", "dos_backward_kernel", "nos_kernel"):
-                if short in k:  # instantiations launched by one call add up
+            for short, pat in (("dos_forward_kernel", "dos_forward_kernel"), ("dos_backward_kernel", "dos_backward_kernel"),
+                               ("dos_backward_kernel", "bwd_gather_kernel"), ("nos_kernel", "nos_kernel")):
+                if pat in k:  # the kernels launched by one call add up (instantiations, gather pass)
                     sha = (source_shas or {}).get(short) or kernel_source_hash(short)
                     rec = traffic.setdefault(short, {"source_sha": sha, "bytes_per_launch": 0.0,
                                                      "read_bytes": 0.0, "write_bytes": 0.0})
@@ -613,6 +616,9 @@ def main():
     G = (2.0 * (dos - target)).contiguous()
     if not args.tiles:
         tile_b, times_b = tune.tune_backward(eps, w, grid, e0, de, G, reps=3)
+    # workspace of the adjoint's two-phase output (0 bytes where it does not apply), allocated once
+    ws_b = torch.empty(max(tetra.backward_workspace_bytes(grid, nb, norb, e0, de, ne, tile=tile_b), 1),
+                       dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 
     stream = torch.cuda.current_stream(dev)
@@ -625,7 +631,7 @@ def main():
         if ev is not None:
             ev[1].record(stream)
         if use_bwd:
-            tetra.dos_backward(eps, w, grid, e0, de, G, grad_eps=ge, grad_w=gw, tile=tile_b)
+            tetra.dos_backward(eps, w, grid, e0, de, G, grad_eps=ge, grad_w=gw, tile=tile_b, workspace=ws_b)
             if ev is not None:
                 ev[2].record(stream)
 
@@ -647,13 +653,14 @@ def main():
     t_bwd = float(bwd_ms.mean()) * 1e-3
 
     if use_bwd and t_bwd > t_fwd:
-        kname, flops, t_k = "dos_backward_kernel", f_bwd, t_bwd
+        # the adjoint pass: its kernel and, where the two-phase output applies, the gather pass
+        kname, klabel, flops, t_k = "dos_backward_kernel", "dos_backward_kernel + bwd_gather_kernel", f_bwd, t_bwd
     else:
-        kname, flops, t_k = "dos_forward_kernel", f_fwd, t_fwd
+        kname, klabel, flops, t_k = "dos_forward_kernel", "dos_forward_kernel", f_fwd, t_fwd
     achieved = flops / t_k / 1e12
     roofline = {
         "bound": "alu",
-        "kernel": kname,
+        "kernel": klabel,
         "achieved": achieved,
         "peak": PEAK_FP32_VALU_TFLOPS,
         "unit": "TFLOP/s",

@@ -120,14 +120,39 @@ tetra_status tetra_dos_forward(const tetra_desc* d, const float* eps, const void
  *                                           float [nb][norb][nk][2]: dL/d(re a), dL/d(im a)
  *                                           = 2 (re a, im a) dL/db, interleaved like the input
  *   flags     TETRA_TILE(shape) or 0; TETRA_KAHAN is accepted and ignored (each output element sums at
- *             most eight partial values); TETRA_DETERMINISTIC gives TETRA_ERR_UNSUPPORTED
+ *             most eight partial values); TETRA_DETERMINISTIC gives TETRA_ERR_UNSUPPORTED (points on
+ *             the boundary of a tile are summed with global float atomics, in no fixed order)
  * At least one of grad_eps, grad_w must be non-NULL. Where an energy E_j equals a corner energy the
  * loss is not differentiable; the one-sided value of the case containing E_j is returned.
- * Allocates nothing.
+ * Allocates nothing. Same as tetra_dos_backward_ws with no workspace.
  */
 tetra_status tetra_dos_backward(const tetra_desc* d, const float* eps, const void* w, int wtype,
                                 const float* w_scale, const float* grad_dos, float* grad_eps,
                                 float* grad_w, unsigned flags, void* stream);
+
+/*
+ * Bytes of device workspace for the two-phase output of tetra_dos_backward_ws: 4 (norb + 1) F nb T,
+ * with T the tiles of the grid and F the face points of one tile (for tile shape (a, b, c):
+ * 2 (b+1)(c+1) + 2 (a-1)(c+1) + 2 (a-1)(b-1)). Returns 0 where the two-phase output does not apply
+ * (a grid side that is not a multiple of the tile's, or only one tile along an axis) and for invalid
+ * arguments. flags as for tetra_dos_backward_ws (the tile shape matters).
+ */
+size_t tetra_dos_backward_workspace(const tetra_desc* d, unsigned flags);
+
+/*
+ * tetra_dos_backward with a caller-owned workspace (device memory of at least
+ * tetra_dos_backward_workspace(d, flags) bytes, contents ignored and overwritten, not used after the
+ * work on the stream ends). Each tile writes the partial sums of its boundary points to its own
+ * slots with plain stores, and a second pass adds the 2 to 8 partials of every boundary grid point in
+ * a fixed order: no zero-fill of the outputs, no atomics, and the gradients are bitwise the same from
+ * run to run, so TETRA_DETERMINISTIC is accepted here. workspace NULL: the atomic path of
+ * tetra_dos_backward (TETRA_DETERMINISTIC then gives TETRA_ERR_UNSUPPORTED). A workspace where the
+ * two-phase output does not apply, or ws_bytes below the size, gives TETRA_ERR_WORKSPACE.
+ * Allocates nothing.
+ */
+tetra_status tetra_dos_backward_ws(const tetra_desc* d, const float* eps, const void* w, int wtype,
+                                   const float* w_scale, const float* grad_dos, float* grad_eps, float* grad_w,
+                                   unsigned flags, void* workspace, size_t ws_bytes, void* stream);
 
 /*
  * Orbital-resolved number of states (eq. BZintegral with X = b of eq. matrixelements and the step

@@ -24,6 +24,7 @@ __all__ = [
     "make_desc",
     "dos_forward",
     "dos_backward",
+    "backward_workspace_bytes",
     "nos_forward",
     "dos_binned",
     "dos",
@@ -112,6 +113,10 @@ def lib():
         L.tetra_dos_binned.restype = i
         L.tetra_dos_backward.argtypes = [ctypes.POINTER(TetraDesc), p, p, i, p, p, p, p, u, p]
         L.tetra_dos_backward.restype = i
+        L.tetra_dos_backward_workspace.argtypes = [ctypes.POINTER(TetraDesc), u]
+        L.tetra_dos_backward_workspace.restype = ctypes.c_size_t
+        L.tetra_dos_backward_ws.argtypes = [ctypes.POINTER(TetraDesc), p, p, i, p, p, p, p, u, p, ctypes.c_size_t, p]
+        L.tetra_dos_backward_ws.restype = i
         L.tetra_dos_batched_workspace.argtypes = [ctypes.POINTER(TetraItem), i, i, u]
         L.tetra_dos_batched_workspace.restype = ctypes.c_size_t
         L.tetra_dos_batched.argtypes = [ctypes.POINTER(TetraItem), i, i, u, p, ctypes.c_size_t, p]
@@ -261,12 +266,24 @@ def dos_forward(eps, w, grid, e0, de, ne, *, w_scale=None, kahan=False, determin
     return out
 
 
+def backward_workspace_bytes(grid, nb, norb, e0, de, ne, *, tile=None):
+    """Device bytes of the adjoint's two-phase output (0 where it does not apply: a grid side not a
+    multiple of the tile's, or a single tile along an axis)."""
+    d = make_desc(grid, nb, norb, e0, de, ne)
+    return int(lib().tetra_dos_backward_workspace(ctypes.byref(d), _tile_flag(tile)))
+
+
 def dos_backward(eps, w, grid, e0, de, grad_dos, *, w_scale=None, need_eps=True, need_w=True,
-                 grad_eps=None, grad_w=None, tile=None):
+                 grad_eps=None, grad_w=None, tile=None, two_phase=True, workspace=None, deterministic=False):
     """``(dL/deps [nb, nk] or None, dL/dw [nb, norb, nk] or None)`` for ``grad_dos = dL/dDOS``.
 
     dL/dw is float32 for float32 or float16 weights (of the dequantised weights) and complex64 for
-    complex amplitudes, ``2 a dL/db`` (the gradient with respect to the real and imaginary parts)."""
+    complex amplitudes, ``2 a dL/db`` (the gradient with respect to the real and imaginary parts).
+
+    ``two_phase`` (where it applies, see ``backward_workspace_bytes``): tile-boundary points go through
+    a workspace (``workspace``, a uint8 device tensor of at least that size, or one allocated here)
+    and a gather pass instead of global atomics; the gradients are then bitwise reproducible and
+    ``deterministic=True`` is accepted (it raises where the two-phase output does not apply)."""
     torch = _torch()
     nk, nb, norb = _shapes(eps, w, grid)
     dev = eps.device
@@ -285,12 +302,22 @@ def dos_backward(eps, w, grid, e0, de, grad_dos, *, w_scale=None, need_eps=True,
     if grad_w is not None:
         _require(grad_w, "grad_w", (nb, norb, nk), (gw_dtype,), dev)
     d = make_desc(grid, nb, norb, e0, de, ne)
-    st = lib().tetra_dos_backward(
+    flags = _tile_flag(tile) | (TETRA_DETERMINISTIC if deterministic else 0)
+    need = int(lib().tetra_dos_backward_workspace(ctypes.byref(d), flags)) if two_phase else 0
+    ws_ptr, ws_bytes = None, 0
+    if need:
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+        elif workspace.dtype != torch.uint8 or workspace.device != dev or workspace.numel() < need \
+                or not workspace.is_contiguous():
+            raise ValueError(f"workspace must be a contiguous uint8 tensor on {dev} of at least {need} bytes")
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel()
+    st = lib().tetra_dos_backward_ws(
         ctypes.byref(d), eps.data_ptr(), w.data_ptr(), wtype,
         w_scale.data_ptr() if w_scale is not None else None, grad_dos.data_ptr(),
         grad_eps.data_ptr() if grad_eps is not None else None,
-        grad_w.data_ptr() if grad_w is not None else None, _tile_flag(tile), _stream_handle(dev))
-    _check("tetra_dos_backward", st)
+        grad_w.data_ptr() if grad_w is not None else None, flags, ws_ptr, ws_bytes, _stream_handle(dev))
+    _check("tetra_dos_backward_ws", st)
     return grad_eps, grad_w
 
 

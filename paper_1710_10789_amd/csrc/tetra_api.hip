@@ -100,9 +100,9 @@ tetra_status tetra_dos_forward(const tetra_desc* d, const float* eps, const void
       tetra::forward(*d, eps, w, wtype, scale_of(wtype, w_scale), dos, scratch, shape, (hipStream_t)stream));
 }
 
-tetra_status tetra_dos_backward(const tetra_desc* d, const float* eps, const void* w, int wtype,
-                                const float* w_scale, const float* grad_dos, float* grad_eps,
-                                float* grad_w, unsigned flags, void* stream) {
+tetra_status tetra_dos_backward_ws(const tetra_desc* d, const float* eps, const void* w, int wtype,
+                                   const float* w_scale, const float* grad_dos, float* grad_eps, float* grad_w,
+                                   unsigned flags, void* workspace, size_t ws_bytes, void* stream) {
   tetra_status st = check_desc(d);
   if (st != TETRA_OK) return st;
   if (!eps || !w || !grad_dos || (!grad_eps && !grad_w)) return TETRA_ERR_ARG;
@@ -110,9 +110,26 @@ tetra_status tetra_dos_backward(const tetra_desc* d, const float* eps, const voi
   if (flags & ~(unsigned)(TETRA_KAHAN | TETRA_DETERMINISTIC | TETRA_TILE_MASK)) return TETRA_ERR_ARG;
   const int shape = (int)((flags & TETRA_TILE_MASK) >> 8);
   if (shape >= tetra::kTileShapes) return TETRA_ERR_ARG;
-  if (flags & TETRA_DETERMINISTIC) return TETRA_ERR_UNSUPPORTED;
+  const size_t need = tetra::backward_workspace_bytes(*d, shape);
+  if (workspace && (need == 0 || ws_bytes < need)) return TETRA_ERR_WORKSPACE;
+  // the two-phase output is deterministic; the atomic one is not
+  if ((flags & TETRA_DETERMINISTIC) && !workspace) return TETRA_ERR_UNSUPPORTED;
   return hip_status(tetra::backward(*d, eps, w, wtype, scale_of(wtype, w_scale), grad_dos, grad_eps, grad_w, shape,
-                                    (hipStream_t)stream));
+                                    workspace, (hipStream_t)stream));
+}
+
+tetra_status tetra_dos_backward(const tetra_desc* d, const float* eps, const void* w, int wtype,
+                                const float* w_scale, const float* grad_dos, float* grad_eps,
+                                float* grad_w, unsigned flags, void* stream) {
+  return tetra_dos_backward_ws(d, eps, w, wtype, w_scale, grad_dos, grad_eps, grad_w, flags, nullptr, 0, stream);
+}
+
+size_t tetra_dos_backward_workspace(const tetra_desc* d, unsigned flags) {
+  if (check_desc(d) != TETRA_OK) return 0;
+  if (flags & ~(unsigned)(TETRA_KAHAN | TETRA_DETERMINISTIC | TETRA_TILE_MASK)) return 0;
+  const int shape = (int)((flags & TETRA_TILE_MASK) >> 8);
+  if (shape >= tetra::kTileShapes) return 0;
+  return tetra::backward_workspace_bytes(*d, shape);
 }
 
 namespace {

@@ -14,13 +14,20 @@
 // four corners the map cube -> corner point is injective across lanes, and four barrier-separated
 // rounds add each lane's per-corner sums into LDS point totals with plain read-modify-writes.
 // A grid point whose eight cubes all belong to the tile is complete in LDS and written with a plain
-// store; a point on the tile's boundary receives its partial sum with one global float atomic per
-// value (the outputs are zero-filled first). On an axis short enough for the periodic wrap to repeat
-// a point inside one tile, every point goes through the atomics, which sums the repeats.
+// store. A point on the tile's boundary gets its partial sums one of two ways:
+//  * two-phase (a workspace, grid sides multiples of the tile's, more than one tile per axis): the
+//    tile stores them in its face slots (tetra_faces.h) with plain stores, and a gather pass adds the
+//    2 to 8 partials of every boundary grid point in a fixed order and writes the outputs. Nothing
+//    is zero-filled, no atomics, and the result does not depend on the order workgroups run in;
+//  * otherwise one global float atomic per value into zero-filled outputs. On an axis short enough
+//    for the periodic wrap to repeat a point inside one tile, every point goes through the atomics,
+//    which sums the repeats.
 
+#include <algorithm>
 #include <type_traits>
 
 #include "tetra_device.h"
+#include "tetra_faces.h"
 #include "tetra_internal.h"
 #include "tetra_weights.h"
 
@@ -40,6 +47,8 @@ struct BwdArgs {
   const float* G;
   float* grad_eps;
   float* grad_w;  // [nb][norb][nk], or [nb][norb][nk][2] (re, im) for complex amplitudes
+  float* part;    // two-phase output: [unit][1 + norb][nface] face partial sums, or null
+  int nface;      // face points per tile
   int wtype;
   int n1, n2, n3, ne;
   float e0, de, inv_de, V;
@@ -117,9 +126,10 @@ __global__ __launch_bounds__(NT) void dos_backward_kernel(BwdArgs a) {
     emin = fminf(emin, s_red[i]);
     emax = fmaxf(emax, s_red[NT / 64 + i]);
   }
-  if (!(emin <= emax)) return;  // no finite energy: nothing to add to the zero-filled outputs
-  int J0, J1;
-  range_window(emin, emax, a.e0, a.inv_de, a.ne, J0, J1);
+  // No finite energy: nothing to add, but the zero sums are still written (the two-phase output
+  // does not zero-fill).
+  int J0 = 0, J1 = -1;
+  if (emin <= emax) range_window(emin, emax, a.e0, a.inv_de, a.ne, J0, J1);
 
   const int cz = tid % TZ, cy = (tid / TZ) % TY, cx = tid / (TZ * TY);
   const bool active = (x0 + cx < a.n1) && (y0 + cy < a.n2) && (z0 + cz < a.n3);
@@ -271,12 +281,20 @@ __global__ __launch_bounds__(NT) void dos_backward_kernel(BwdArgs a) {
     __syncthreads();
   }
 
-  // Interior points are complete: plain stores. Boundary points: one global atomic per non-zero value.
+  // Interior points are complete: plain stores. Boundary points: face slots (two-phase), or one
+  // global atomic per non-zero value.
   const bool no_repeat = a.n1 > TX && a.n2 > TY && a.n3 > TZ;
   for (int p = tid; p < NP; p += NT) {
     const int pz = p % PZ, py = (p / PZ) % PY, px = p / (PZ * PY);
     const bool interior = no_repeat && px >= 1 && px < TX && py >= 1 && py < TY && pz >= 1 && pz < TZ &&
                           x0 + px < a.n1 && y0 + py < a.n2 && z0 + pz < a.n3;
+    if (a.part && !interior) {
+      float* dst = a.part + (int64_t)unit * (NORB + 1) * a.nface + face_index(px, py, pz, TX, TY, TZ);
+      const float* src = &s_pt[p * (NORB + 1)];
+#pragma unroll
+      for (int v = 0; v <= NORB; ++v) dst[(int64_t)v * a.nface] = src[v];
+      continue;
+    }
     const int64_t k = ((int64_t)wrap(x0 + px, a.n1) * a.n2 + wrap(y0 + py, a.n2)) * a.n3 + wrap(z0 + pz, a.n3);
     const float* src = &s_pt[p * (NORB + 1)];
     if (a.grad_eps) {
@@ -308,6 +326,72 @@ __global__ __launch_bounds__(NT) void dos_backward_kernel(BwdArgs a) {
   }
 }
 
+// Second phase of the two-phase output: every (band, grid point) not complete in its own tile adds the
+// face partials of the tiles holding it (face_tiles on each axis, a fixed order) and writes the
+// outputs.
+struct GatherArgs {
+  const void* w;  // complex amplitudes for the chain to (re, im); unused otherwise
+  const float* part;
+  float* grad_eps;
+  float* grad_w;
+  int n1, n2, n3, nb;
+  int TX, TY, TZ;
+  int t1, t2, t3, ntiles, nface;
+};
+
+template <int NORB, typename WT>
+__global__ __launch_bounds__(256) void bwd_gather_kernel(GatherArgs g) {
+  const int64_t nk = (int64_t)g.n1 * g.n2 * g.n3;
+  const int64_t total = nk * g.nb;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int band = (int)(i / nk);
+    const int64_t k = i - (int64_t)band * nk;
+    const int z = (int)(k % g.n3), y = (int)((k / g.n3) % g.n2), x = (int)(k / ((int64_t)g.n2 * g.n3));
+    int ta[2], pa[2], tb[2], pb[2], tc[2], pc[2];
+    const int na = face_tiles(x, g.TX, g.t1, ta, pa);
+    const int nbt = face_tiles(y, g.TY, g.t2, tb, pb);
+    const int nc = face_tiles(z, g.TZ, g.t3, tc, pc);
+    if (pa[0] && pb[0] && pc[0]) continue;  // complete in its own tile, stored by the adjoint kernel
+    float acc[NORB + 1];
+#pragma unroll
+    for (int v = 0; v <= NORB; ++v) acc[v] = 0.0f;
+    for (int ia = 0; ia < na; ++ia)
+      for (int ib = 0; ib < nbt; ++ib)
+        for (int ic = 0; ic < nc; ++ic) {
+          const int tile = (ta[ia] * g.t2 + tb[ib]) * g.t3 + tc[ic];
+          const float* src = g.part + ((int64_t)band * g.ntiles + tile) * (NORB + 1) * g.nface +
+                             face_index(pa[ia], pb[ib], pc[ic], g.TX, g.TY, g.TZ);
+#pragma unroll
+          for (int v = 0; v <= NORB; ++v) acc[v] += src[(int64_t)v * g.nface];
+        }
+    if (g.grad_eps) g.grad_eps[(int64_t)band * nk + k] = acc[0];
+    if (g.grad_w) {
+#pragma unroll
+      for (int m = 0; m < NORB; ++m) {
+        const int64_t idx = ((int64_t)band * NORB + m) * nk + k;
+        if constexpr (std::is_same<WT, float2>::value) {
+          const float2 amp = static_cast<const float2*>(g.w)[idx];
+          const float g2 = 2.0f * acc[1 + m];
+          *reinterpret_cast<float2*>(&g.grad_w[2 * idx]) = make_float2(g2 * amp.x, g2 * amp.y);
+        } else {
+          g.grad_w[idx] = acc[1 + m];
+        }
+      }
+    }
+  }
+}
+
+template <int NORB>
+hipError_t launch_gather(const GatherArgs& g, int wtype, hipStream_t s) {
+  const int64_t total = (int64_t)g.n1 * g.n2 * g.n3 * g.nb;
+  const int blocks = (int)std::min<int64_t>((total + 255) / 256, 8192);
+  if (wtype == TETRA_W_C32)
+    hipLaunchKernelGGL((bwd_gather_kernel<NORB, float2>), dim3(blocks), dim3(256), 0, s, g);
+  else
+    hipLaunchKernelGGL((bwd_gather_kernel<NORB, float>), dim3(blocks), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
 template <int NORB>
 hipError_t launch_bwd(const BwdArgs& a, int grid, hipStream_t s) {
   if (a.wtype == TETRA_W_F16)
@@ -321,8 +405,15 @@ hipError_t launch_bwd(const BwdArgs& a, int grid, hipStream_t s) {
 
 }  // namespace
 
+size_t backward_workspace_bytes(const tetra_desc& d, int shape) {
+  const TileShape sh = tile_shape(shape);
+  if (d.n1 % sh.x || d.n2 % sh.y || d.n3 % sh.z || d.n1 <= sh.x || d.n2 <= sh.y || d.n3 <= sh.z) return 0;
+  const size_t units = (size_t)(d.n1 / sh.x) * (d.n2 / sh.y) * (d.n3 / sh.z) * d.nb;
+  return units * (size_t)(d.norb + 1) * face_count(sh.x, sh.y, sh.z) * sizeof(float);
+}
+
 hipError_t backward(const tetra_desc& d, const float* eps, const void* w, int wtype, const float* w_scale,
-                    const float* G, float* grad_eps, float* grad_w, int shape, hipStream_t s) {
+                    const float* G, float* grad_eps, float* grad_w, int shape, void* workspace, hipStream_t s) {
   BwdArgs a;
   a.wtype = wtype;
   a.eps = eps;
@@ -351,14 +442,38 @@ hipError_t backward(const tetra_desc& d, const float* eps, const void* w, int wt
   a.per_xcd = (a.nunits + NXCD - 1) / NXCD;
   const int grid = a.per_xcd * NXCD;
   const int64_t nk = (int64_t)d.n1 * d.n2 * d.n3;
+  const bool two_phase = workspace && backward_workspace_bytes(d, shape) > 0;
+  a.part = two_phase ? static_cast<float*>(workspace) : nullptr;
+  a.nface = face_count(sh.x, sh.y, sh.z);
+  GatherArgs g;
+  g.w = w;
+  g.part = a.part;
+  g.grad_eps = grad_eps;
+  g.grad_w = grad_w;
+  g.n1 = d.n1;
+  g.n2 = d.n2;
+  g.n3 = d.n3;
+  g.nb = d.nb;
+  g.TX = sh.x;
+  g.TY = sh.y;
+  g.TZ = sh.z;
+  g.t1 = a.t1;
+  g.t2 = a.t2;
+  g.t3 = a.t3;
+  g.ntiles = a.ntiles;
+  g.nface = a.nface;
   hipError_t e = hipSuccess;
-  if (grad_eps) e = fill_zero(grad_eps, nk * d.nb, s);
-  if (e == hipSuccess && grad_w) e = fill_zero(grad_w, nk * d.nb * d.norb * (wtype == TETRA_W_C32 ? 2 : 1), s);
-  if (e != hipSuccess) return e;
+  if (!two_phase) {
+    if (grad_eps) e = fill_zero(grad_eps, nk * d.nb, s);
+    if (e == hipSuccess && grad_w) e = fill_zero(grad_w, nk * d.nb * d.norb * (wtype == TETRA_W_C32 ? 2 : 1), s);
+    if (e != hipSuccess) return e;
+  }
   switch (d.norb) {
-#define TETRA_CASE(N) \
-  case N:             \
-    return launch_bwd<N>(a, grid, s);
+#define TETRA_CASE(N)                                \
+  case N:                                            \
+    e = launch_bwd<N>(a, grid, s);                   \
+    if (e == hipSuccess && two_phase) e = launch_gather<N>(g, wtype, s); \
+    return e;
     TETRA_CASE(1) TETRA_CASE(2) TETRA_CASE(3) TETRA_CASE(4) TETRA_CASE(5) TETRA_CASE(6) TETRA_CASE(7)
     TETRA_CASE(8) TETRA_CASE(9) TETRA_CASE(10) TETRA_CASE(11) TETRA_CASE(12) TETRA_CASE(13)
     TETRA_CASE(14) TETRA_CASE(15) TETRA_CASE(16)

@@ -39,8 +39,12 @@ inline size_t forward_exact_scratch_bytes(const tetra_desc& d) { return 256 + 8 
 // Number of states (binned = false) or bin-averaged DOS (binned = true) into out[ne][norb].
 hipError_t nos(const tetra_desc& d, const float* eps, const void* w, int wtype, const float* w_scale, float* out,
                bool binned, int shape, hipStream_t s);
-// grad_w is [nb][norb][nk] floats, or [nb][norb][nk][2] for complex amplitudes.
+// grad_w is [nb][norb][nk] floats, or [nb][norb][nk][2] for complex amplitudes. With a workspace of
+// backward_workspace_bytes(d, shape) bytes (non-zero only where the grid sides are multiples of the
+// tile's, with more than one tile per axis), tile-boundary points take the two-phase output; with
+// none, global atomics into zero-filled outputs.
+size_t backward_workspace_bytes(const tetra_desc& d, int shape);
 hipError_t backward(const tetra_desc& d, const float* eps, const void* w, int wtype, const float* w_scale,
-                    const float* G, float* grad_eps, float* grad_w, int shape, hipStream_t s);
+                    const float* G, float* grad_eps, float* grad_w, int shape, void* workspace, hipStream_t s);
 
 }  // namespace tetra

@@ -29,7 +29,8 @@ def L():
 
 def test_header_declares_the_entry_points():
     names = _declared_functions()
-    for n in ("tetra_dos_forward", "tetra_dos_backward", "tetra_dos_batched", "tetra_dos_batched_workspace",
+    for n in ("tetra_dos_forward", "tetra_dos_backward", "tetra_dos_backward_ws", "tetra_dos_backward_workspace",
+              "tetra_dos_batched", "tetra_dos_batched_workspace",
               "tetra_nos_forward", "tetra_dos_binned", "tetra_status_string", "tetra_last_hip_error",
               "tetra_version"):
         assert n in names
@@ -181,3 +182,42 @@ def test_probe_rejects_bad_arguments(L):
     assert L.tetra_probe_lds_atomics(4, 0, FAKE, None) == -1
     assert L.tetra_probe_lds_atomics(4, 10, None, None) == -1
     assert L.tetra_probe_lds_atomics((1 << 24) + 1, 10, FAKE, None) == -1
+
+
+def test_backward_workspace_sizes(L):
+    """tetra_dos_backward_workspace: 4 (norb + 1) F nb T bytes where the two-phase output applies
+    (grid sides multiples of the tile's, more than one tile per axis), else 0."""
+    shapes = [(4, 4, 16), (8, 8, 4), (4, 8, 8), (8, 4, 8), (4, 16, 4), (16, 4, 4)]
+    for sid, (a, b, c) in enumerate(shapes):
+        faces = 2 * (b + 1) * (c + 1) + 2 * (a - 1) * (c + 1) + 2 * (a - 1) * (b - 1)
+        assert faces == (a + 1) * (b + 1) * (c + 1) - (a - 1) * (b - 1) * (c - 1)
+        d = tetra.make_desc((64, 64, 64), 8, 8, -1.0, 0.01, 1000)
+        tiles = (64 // a) * (64 // b) * (64 // c)
+        assert L.tetra_dos_backward_workspace(ctypes.byref(d), sid << 8) == 4 * 9 * faces * 8 * tiles
+        assert tetra.backward_workspace_bytes((64, 64, 64), 8, 8, -1.0, 0.01, 1000, tile=sid) == 4 * 9 * faces * 8 * tiles
+        for grid in ((a, 2 * b, 2 * c), (2 * a, 2 * b, c), (2 * a + 1, 2 * b, 2 * c), (2 * a, 2 * b, 3 * c - 1)):
+            d = tetra.make_desc(grid, 2, 3, -1.0, 0.01, 100)
+            assert L.tetra_dos_backward_workspace(ctypes.byref(d), sid << 8) == 0, (sid, grid)
+    d = good()
+    d.ne = 0
+    assert L.tetra_dos_backward_workspace(ctypes.byref(d), 0) == 0
+    assert L.tetra_dos_backward_workspace(ctypes.byref(good()), 0x10) == 0  # unknown flag
+    assert L.tetra_dos_backward_workspace(ctypes.byref(good()), 6 << 8) == 0  # no such tile shape
+
+
+def _bwd_ws(L, d, ws, ws_bytes, flags=0):
+    return L.tetra_dos_backward_ws(ctypes.byref(d), FAKE, FAKE, 0, None, FAKE, FAKE, FAKE, flags, ws, ws_bytes, None)
+
+
+def test_backward_ws_rejects_before_launch(L):
+    d = tetra.make_desc((8, 8, 32), 2, 3, -1.0, 0.01, 100)
+    need = L.tetra_dos_backward_workspace(ctypes.byref(d), 0)
+    assert need > 0
+    assert _bwd_ws(L, d, FAKE, need - 1) == -3  # too small
+    ragged = tetra.make_desc((6, 8, 32), 2, 3, -1.0, 0.01, 100)
+    assert _bwd_ws(L, ragged, FAKE, 1 << 30) == -3  # the two-phase output does not apply
+    assert _bwd_ws(L, ragged, None, 0, flags=2) == -2  # deterministic needs the two-phase output
+    assert _bwd_ws(L, d, None, 0, flags=2) == -2
+    bad = tetra.make_desc((8, 8, 32), 2, 3, -1.0, 0.0, 100)
+    assert _bwd_ws(L, bad, FAKE, need) == -1
+    assert L.tetra_dos_backward_ws(ctypes.byref(d), FAKE, FAKE, 0, None, FAKE, None, None, 0, FAKE, need, None) == -1
