@@ -136,6 +136,14 @@ __global__ __launch_bounds__(NT) void dos_backward_kernel(BwdArgs a) {
   const int pbase = (cx * PY + cy) * PZ + cz;
   auto point_offset = [PY, PZ](int s) { return (s & 1) * (PY * PZ) + ((s >> 1) & 1) * PZ + (s >> 2); };
 
+  // Corners 2 and 5 of the cube (its body diagonal) belong to all six tetrahedra of Table I: their sums
+  // stay in registers over every tetrahedron and energy pass and go to LDS once at the end, so each
+  // tetrahedron needs only two rounds (its other two corners): 2 % faster at norb = 8. It costs 2 to
+  // 45 VGPRs; orbital counts where that would lower the waves per SIMD keep four rounds.
+  constexpr bool DIAG = !(NORB == 2 || NORB == 5 || NORB == 9 || NORB == 10 || NORB == 16);
+  float diag2[NORB + 1], diag5[NORB + 1];
+#pragma unroll
+  for (int v = 0; v <= NORB; ++v) diag2[v] = diag5[v] = 0.0f;
   for (int c0 = J0; c0 <= J1; c0 += LC) {
     const int c1 = min(c0 + LC - 1, J1);
     const int L = c1 - c0 + 1;
@@ -268,15 +276,44 @@ __global__ __launch_bounds__(NT) void dos_backward_kernel(BwdArgs a) {
         unsort_rows(sw, gb);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
+          const int corner = (slots >> (4 * q)) & 7;  // uniform: t is the same for every lane
+          if (DIAG && corner == 2) {
+            diag2[0] += ge[q][0];
+#pragma unroll
+            for (int m = 0; m < NORB; ++m) diag2[1 + m] += gb[q][m];
+            continue;
+          }
+          if (DIAG && corner == 5) {
+            diag5[0] += ge[q][0];
+#pragma unroll
+            for (int m = 0; m < NORB; ++m) diag5[1 + m] += gb[q][m];
+            continue;
+          }
           __syncthreads();
           if (any) {
-            float* dst = &s_pt[(pbase + point_offset((slots >> (4 * q)) & 7)) * (NORB + 1)];
+            float* dst = &s_pt[(pbase + point_offset(corner)) * (NORB + 1)];
             dst[0] += ge[q][0];
 #pragma unroll
             for (int m = 0; m < NORB; ++m) dst[1 + m] += gb[q][m];
           }
         }
       }
+    }
+    __syncthreads();
+  }
+  if constexpr (DIAG) {
+    // the two diagonal corners, one round each (a lane's sums are zero where it had nothing to add)
+    __syncthreads();
+    if (active) {
+      float* dst = &s_pt[(pbase + point_offset(2)) * (NORB + 1)];
+#pragma unroll
+      for (int v = 0; v <= NORB; ++v) dst[v] += diag2[v];
+    }
+    __syncthreads();
+    if (active) {
+      float* dst = &s_pt[(pbase + point_offset(5)) * (NORB + 1)];
+#pragma unroll
+      for (int v = 0; v <= NORB; ++v) dst[v] += diag5[v];
     }
     __syncthreads();
   }
