@@ -141,8 +141,8 @@ size_t tetra_dos_backward_workspace(const tetra_desc* d, unsigned flags);
 
 /*
  * tetra_dos_backward with a caller-owned workspace (device memory of at least
- * tetra_dos_backward_workspace(d, flags) bytes, contents ignored and overwritten, not used after the
- * work on the stream ends). Each tile writes the partial sums of its boundary points to its own
+ * tetra_dos_backward_workspace(d, flags) bytes, 16-byte aligned (TETRA_ERR_ARG otherwise), contents
+ * ignored and overwritten, not used after the work on the stream ends). Each tile writes the partial sums of its boundary points to its own
  * slots with plain stores, and a second pass adds the 2 to 8 partials of every boundary grid point in
  * a fixed order: no zero-fill of the outputs, no atomics, and the gradients are bitwise the same from
  * run to run, so TETRA_DETERMINISTIC is accepted here. workspace NULL: the atomic path of

@@ -1,6 +1,7 @@
 // C ABI entry points (include/tetra.h): argument validation on the host, then kernel launches.
 
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -112,6 +113,7 @@ tetra_status tetra_dos_backward_ws(const tetra_desc* d, const float* eps, const 
   if (shape >= tetra::kTileShapes) return TETRA_ERR_ARG;
   const size_t need = tetra::backward_workspace_bytes(*d, shape);
   if (workspace && (need == 0 || ws_bytes < need)) return TETRA_ERR_WORKSPACE;
+  if (reinterpret_cast<uintptr_t>(workspace) % 16 != 0) return TETRA_ERR_ARG;
   // the two-phase output is deterministic; the atomic one is not
   if ((flags & TETRA_DETERMINISTIC) && !workspace) return TETRA_ERR_UNSUPPORTED;
   return hip_status(tetra::backward(*d, eps, w, wtype, scale_of(wtype, w_scale), grad_dos, grad_eps, grad_w, shape,

@@ -214,6 +214,7 @@ def test_backward_ws_rejects_before_launch(L):
     need = L.tetra_dos_backward_workspace(ctypes.byref(d), 0)
     assert need > 0
     assert _bwd_ws(L, d, FAKE, need - 1) == -3  # too small
+    assert _bwd_ws(L, d, FAKE + 4, need) == -1  # misaligned
     ragged = tetra.make_desc((6, 8, 32), 2, 3, -1.0, 0.01, 100)
     assert _bwd_ws(L, ragged, FAKE, 1 << 30) == -3  # the two-phase output does not apply
     assert _bwd_ws(L, ragged, None, 0, flags=2) == -2  # deterministic needs the two-phase output
