@@ -47,7 +47,7 @@ struct BwdArgs {
   const float* G;
   float* grad_eps;
   float* grad_w;  // [nb][norb][nk], or [nb][norb][nk][2] (re, im) for complex amplitudes
-  float* part;    // two-phase output: [unit][1 + norb][nface] face partial sums, or null
+  float* part;    // two-phase output: [unit][nface][1 + norb] face partial sums, or null
   int nface;      // face points per tile
   int wtype;
   int n1, n2, n3, ne;
@@ -326,10 +326,10 @@ __global__ __launch_bounds__(NT) void dos_backward_kernel(BwdArgs a) {
     const bool interior = no_repeat && px >= 1 && px < TX && py >= 1 && py < TY && pz >= 1 && pz < TZ &&
                           x0 + px < a.n1 && y0 + py < a.n2 && z0 + pz < a.n3;
     if (a.part && !interior) {
-      float* dst = a.part + (int64_t)unit * (NORB + 1) * a.nface + face_index(px, py, pz, TX, TY, TZ);
+      float* dst = a.part + ((int64_t)unit * a.nface + face_index(px, py, pz, TX, TY, TZ)) * (NORB + 1);
       const float* src = &s_pt[p * (NORB + 1)];
 #pragma unroll
-      for (int v = 0; v <= NORB; ++v) dst[(int64_t)v * a.nface] = src[v];
+      for (int v = 0; v <= NORB; ++v) dst[v] = src[v];
       continue;
     }
     const int64_t k = ((int64_t)wrap(x0 + px, a.n1) * a.n2 + wrap(y0 + py, a.n2)) * a.n3 + wrap(z0 + pz, a.n3);
@@ -396,10 +396,10 @@ __global__ __launch_bounds__(256) void bwd_gather_kernel(GatherArgs g) {
       for (int ib = 0; ib < nbt; ++ib)
         for (int ic = 0; ic < nc; ++ic) {
           const int tile = (ta[ia] * g.t2 + tb[ib]) * g.t3 + tc[ic];
-          const float* src = g.part + ((int64_t)band * g.ntiles + tile) * (NORB + 1) * g.nface +
-                             face_index(pa[ia], pb[ib], pc[ic], g.TX, g.TY, g.TZ);
+          const float* src = g.part + (((int64_t)band * g.ntiles + tile) * g.nface +
+                                       face_index(pa[ia], pb[ib], pc[ic], g.TX, g.TY, g.TZ)) * (NORB + 1);
 #pragma unroll
-          for (int v = 0; v <= NORB; ++v) acc[v] += src[(int64_t)v * g.nface];
+          for (int v = 0; v <= NORB; ++v) acc[v] += src[v];
         }
     if (g.grad_eps) g.grad_eps[(int64_t)band * nk + k] = acc[0];
     if (g.grad_w) {
