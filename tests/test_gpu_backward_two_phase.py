@@ -9,7 +9,9 @@ is a multiple of the tile's with more than one tile per axis.
 * bitwise reproducible from run to run (``deterministic=True`` accepted), and within 1e-6 of the
   largest gradient of the atomic path on the same inputs;
 * forward and adjoint captured in one HIP graph and replayed four times with eager work between
-  replays, every replay against the eager result."""
+  replays, every replay against the eager result;
+* one caller-owned workspace reused across problems of different sizes and tile shapes, bit for bit
+  the result of a fresh one."""
 import numpy as np
 import pytest
 
@@ -192,3 +194,34 @@ def test_forward_and_two_phase_adjoint_in_one_graph(torch_dev):
         torch.cuda.synchronize()
         assert torch.allclose(dos, ref[0], rtol=1e-6, atol=1e-6 * float(ref[0].abs().max())), rep
         assert torch.equal(ge, ref[1]) and torch.equal(gw, ref[2]), rep  # the adjoint is reproducible
+
+
+def test_workspace_reused_across_problems(torch_dev):
+    """One caller-owned workspace, sized for the larger problem, used for two problems in a row (the
+    second smaller, on another tile shape) and then for the first again: each result equals that of
+    a fresh workspace bit for bit, so nothing depends on what the workspace held before."""
+    torch, dev = torch_dev
+    import paper_1710_10789_amd as tetra
+
+    probs = []
+    for grid, tile, ne, seed in (((8, 8, 32), 0, 200, 81), ((16, 8, 16), 3, 90, 82)):
+        eps, w = synth.band_structure(4, seed, grid, cache=False)
+        e0, de = synth.energy_grid(eps, ne)
+        G = torch.from_numpy(np.random.default_rng(seed).normal(size=(ne, 4)).astype(np.float32)).to(dev)
+        probs.append((torch.from_numpy(eps).to(dev), torch.from_numpy(w).to(dev), grid, e0, de, G, tile))
+    sizes = [tetra.backward_workspace_bytes(p[2], p[0].shape[0], 4, p[3], p[4], p[5].shape[0], tile=p[6]) for p in probs]
+    assert sizes[0] > sizes[1] > 0
+    ws = torch.full((sizes[0],), 0xAB, dtype=torch.uint8, device=dev)
+    print("[case] workspace reuse, two problems", flush=True)
+    results = []
+    for p in (probs[0], probs[1], probs[0]):
+        te, tw, grid, e0, de, G, tile = p
+        shared = tetra.dos_backward(te, tw, grid, e0, de, G, tile=tile, workspace=ws)
+        fresh = tetra.dos_backward(te, tw, grid, e0, de, G, tile=tile, deterministic=True)
+        torch.cuda.synchronize()
+        assert torch.equal(shared[0], fresh[0]) and torch.equal(shared[1], fresh[1])
+        results.append(shared)
+    assert torch.equal(results[0][0], results[2][0]) and torch.equal(results[0][1], results[2][1])
+    with pytest.raises(ValueError):
+        te, tw, grid, e0, de, G, tile = probs[0]
+        tetra.dos_backward(te, tw, grid, e0, de, G, tile=tile, workspace=ws[: sizes[0] - 1])
