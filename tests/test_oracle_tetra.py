@@ -266,3 +266,48 @@ def test_weight_derivatives_match_finite_differences(oracle_lib):
                 em[i] -= h
                 fd = (oracle_lib.corner_weights(ep, E, VOL)[1] - oracle_lib.corner_weights(em, E, VOL)[1]) / (2 * h)
                 np.testing.assert_allclose(dg[:, i], fd, rtol=2e-5, atol=1e-7 * VOL)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_tet_contributions_on_unsorted_corners_equal_geometry(oracle_lib, seed):
+    """One tetrahedron's contributions with its corners in arbitrary order (Sec. II.C, summed with
+    the corner values b as in eq. tetracontriborbitalresolved): sum_l b_l w_l(E) equals the
+    clipped-volume integral and sum_l b_l dw_l/dE the section integral of the linear interpolant of b,
+    both from plane geometry in the corners' own order. Distinct b per corner, so an unsorted b or a
+    density weight in place of an integrated one fails."""
+    rng = np.random.default_rng(300 + seed)
+    done = 0
+    while done < 6:
+        e = rng.uniform(-1, 1, 4)
+        if np.min(np.diff(np.sort(e))) < 1e-3:
+            continue
+        X = rng.normal(size=(4, 3))
+        if volume(X) < 0.05:
+            continue
+        b = rng.uniform(0.1, 1.0, 4)
+        es = np.sort(e)
+        Es = list(_energies_inside(es, rng, 2)) + [es[0] - 0.3, es[3] + 0.3]
+        for E in Es:
+            ref_n = float(b @ corner_nos(X, e, E, VOL))
+            ref_d = float(b @ corner_dos(X, e, E, VOL))
+            assert oracle_lib.tet_nos(e, b, E, VOL) == pytest.approx(ref_n, rel=1e-9, abs=1e-12 * VOL)
+            assert oracle_lib.tet_dos(e, b, E, VOL) == pytest.approx(ref_d, rel=1e-9, abs=1e-12 * VOL)
+        done += 1
+
+
+def test_tet_nos_permutation_invariance_and_limits(oracle_lib):
+    """Permuting the (energy, b) corner pairs leaves sum_l b_l w_l unchanged; below E1 it is zero and
+    above E4 it is V_T/(4 V_G) times the sum of the b values (Sec. II.C, fifth case)."""
+    import itertools
+
+    rng = np.random.default_rng(12)
+    for _ in range(10):
+        e = rng.uniform(-1, 1, 4)
+        b = rng.uniform(0, 1, 4)
+        assert oracle_lib.tet_nos(e, b, e.min() - 0.1, VOL) == 0.0
+        assert oracle_lib.tet_nos(e, b, e.max() + 0.1, VOL) == pytest.approx(VOL / 4 * b.sum(), rel=1e-14)
+        for E in np.linspace(e.min(), e.max(), 7)[1:-1]:
+            ref = oracle_lib.tet_nos(e, b, E, VOL)
+            for p in itertools.permutations(range(4)):
+                p = list(p)
+                assert oracle_lib.tet_nos(e[p], b[p], E, VOL) == pytest.approx(ref, rel=1e-13, abs=1e-16)
