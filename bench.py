@@ -164,15 +164,15 @@ def load_traffic(kernel):
 
 
 def cpu_baseline(eps, w, grid, e0, de, ne, mode, G, gpu_fn):
-    """The FP64 oracle timed on the host cores on the same inputs (a full pass is ~10 s of CPU work:
-    its forward splits over k-slabs, its backward over bands, so both legs get min(cores, nb)
-    threads), and its forward on one core (mean of three runs)."""
+    """The FP64 oracle timed on every host core available to this process (its forward splits over
+    k-slabs, its backward over (band, slab) tasks) on the whole workload, and its forward on one core,
+    the mean of five runs as in the paper's CPU protocol (Sec. IV.A)."""
     import oracle
 
     oracle.build()
-    nb = eps.shape[0]
-    cores = min(len(os.sched_getaffinity(0)), nb)
+    cores = len(os.sched_getaffinity(0))
     n1, n2, n3 = grid
+    nb = eps.shape[0]
     dense = 6 * n1 * n2 * n3 * nb * ne
     t0 = time.perf_counter()
     ref, _ = oracle.dos(eps, w, grid, e0, de, ne, nthreads=cores)
@@ -182,23 +182,24 @@ def cpu_baseline(eps, w, grid, e0, de, ne, mode, G, gpu_fn):
     t2 = time.perf_counter()
     got = gpu_fn()
     err = float(np.abs(got - ref).max() / np.abs(ref).max())
-    # the paper's CPU reference (Sec. IV.A) runs on one core; three runs here (it takes five) keep
-    # this leg near ten seconds
+    print(f"[bench] oracle on {cores} threads: fwd {t1 - t0:.2f} s, bwd {t2 - t1:.2f} s", file=sys.stderr, flush=True)
     t1s = []
-    for _ in range(3):
+    for _ in range(5):
         t = time.perf_counter()
         oracle.dos(eps, w, grid, e0, de, ne, nthreads=1)
         t1s.append(time.perf_counter() - t)
+        print(f"[bench] one-core oracle forward {t1s[-1]:.2f} s", file=sys.stderr, flush=True)
     return {
         "value": dense / (t2 - t0),
         "unit": "updates/s",
         "cores": cores,
         "kind": "oracle",
         "sample": f"the whole workload, one {'forward + backward' if mode == 'fwdbwd' else 'forward'} pass "
-                  f"(fwd {t1 - t0:.2f} s, bwd {t2 - t1:.2f} s), FP64",
+                  f"(fwd {t1 - t0:.2f} s, bwd {t2 - t1:.2f} s), FP64, {cores} threads",
         "fwd_value": dense / (t1 - t0),
         "gpu_fwd_err_vs_oracle": err,
         "single_core_fwd_s": float(np.mean(t1s)),
+        "single_core_fwd_runs_s": [float(x) for x in t1s],
     }
 
 
@@ -303,8 +304,8 @@ def bench_precision(args, torch, tetra, dev):
     runs = {
         "fp32": lambda: tetra.dos_forward(eps, w, grid, e0, de, ne, out=out, tile=tile),
         "fp16": lambda: tetra.dos_forward(eps, w16, grid, e0, de, ne, w_scale=scale, out=out, tile=tile),
-        "fp16_exact": lambda: tetra.dos_forward(eps, w16, grid, e0, de, ne, w_scale=scale, out=out, kahan=True),
-        "fp32_exact": lambda: tetra.dos_forward(eps, w, grid, e0, de, ne, out=out, kahan=True),
+        "fp16_exact": lambda: tetra.dos_forward(eps, w16, grid, e0, de, ne, w_scale=scale, out=out, exact=True),
+        "fp32_exact": lambda: tetra.dos_forward(eps, w, grid, e0, de, ne, out=out, exact=True),
     }
     print("[precision] timing", file=sys.stderr, flush=True)
     ms = {k: _time_events(torch, f, args.steps, args.warmup) for k, f in runs.items()}
@@ -674,7 +675,9 @@ def main():
     # (two orbitals per word), timed against the conflict-free rate of the probe kernel
     cus = torch.cuda.get_device_properties(dev).multi_processor_count
     p_blocks, p_iters = cus * 40, 1024
-    ms_probe = _time_events(torch, lambda: tetra.probe_lds_atomics(p_blocks, p_iters, device=dev), 5, 2)
+    from paper_1710_10789_amd import probe
+
+    ms_probe = _time_events(torch, lambda: probe.probe_lds_atomics(p_blocks, p_iters, device=dev), 5, 2)
     rate = p_blocks * 256 * 4 * p_iters / (ms_probe * 1e-3)
     fwd_atomics = uwin * ((norb + 1) // 2)
     lds_ceiling = {"lane_atomics_per_s": rate, "forward_lane_atomics": fwd_atomics,

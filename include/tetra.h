@@ -66,22 +66,26 @@ typedef enum {
 
 /* Flag bits. */
 enum {
-  /* Compensated accumulation. Workgroup histograms are always summed exactly (64-bit fixed point
-   * in LDS); with this flag the cross-workgroup sum is exact as well (a bound pre-pass fixes one
-   * common scale, partial sums are added as 64-bit integers), so the only rounding left is that of
-   * each FP32 contribution and the result is bitwise reproducible. tetra_dos_forward then uses a
-   * library-owned device buffer of 256 + 8*ne*norb bytes, allocated on the first such call on a
-   * device and kept until the process ends; such calls must not overlap on one device. The adjoint
-   * sums at most eight partial values per output element and ignores the flag. */
-  TETRA_KAHAN = 1u,
-  /* Bitwise reproducible result. tetra_dos_forward takes the exact path of TETRA_KAHAN for it (same
-   * buffer, same result). tetra_dos_backward and tetra_dos_batched do not offer it: their sums across
-   * workgroups are float atomics (TETRA_ERR_UNSUPPORTED). */
+  /* Exact (compensated) accumulation of the forward DOS. Every workgroup sums its contributions
+   * exactly in a 64-bit fixed point of its own (LDS); with this flag the cross-workgroup sum is
+   * exact as well: a bound pass fixes one common 64-bit fixed point from the largest per-workgroup
+   * bound exponent (an integer maximum), each workgroup's exact sums are rounded once to it and
+   * added with integer atomics. What remains is the FP32 rounding of each contribution and one
+   * rounding per workgroup and element to the common unit, 2^(L-62) of the largest workgroup bound
+   * (rounded up to a power of two) for 2^L >= the number of (tile, band) workgroups. The result is
+   * bitwise reproducible, independent of the order in which workgroups run. Needs a
+   * workspace (tetra_dos_forward_ws). The adjoint sums at most eight partial values per output
+   * element and ignores the flag. */
+  TETRA_EXACT = 1u,
+  TETRA_KAHAN = TETRA_EXACT, /* former name of TETRA_EXACT (same bit) */
+  /* Bitwise reproducible result. tetra_dos_forward_ws takes the exact path of TETRA_EXACT for it
+   * (same workspace, same result); tetra_dos_backward_ws with its two-phase output (a workspace)
+   * is deterministic as well. The atomic path of tetra_dos_backward, tetra_dos_batched and the
+   * number-of-states calls do not offer it (TETRA_ERR_UNSUPPORTED). */
   TETRA_DETERMINISTIC = 2u,
   /* Bits 8..11 select the tile shape of the forward and adjoint kernels (0 = default); an autotuner
    * picks it per problem class. Shapes are TX x TY x TZ cubes along grid axes (1, 2, 3):
-   * 0: 4x4x16, 1: 8x8x4, 2: 4x8x8, 3: 8x4x8, 4: 4x16x4, 5: 16x4x4. TETRA_KAHAN and
-   * TETRA_DETERMINISTIC require shape 0. */
+   * 0: 4x4x16, 1: 8x8x4, 2: 4x8x8, 3: 8x4x8, 4: 4x16x4, 5: 16x4x4. */
   TETRA_TILE_MASK = 0xF00u
 };
 #define TETRA_TILE(v) (((unsigned)(v) & 0xFu) << 8)
@@ -103,12 +107,33 @@ typedef struct {
  *   wtype    TETRA_W_F32, TETRA_W_F16 or TETRA_W_C32
  *   w_scale  device, float [nb]            per-band scale for TETRA_W_F16, else NULL
  *   dos      device, float [ne][norb]      result, overwritten
- *   flags    TETRA_KAHAN, TETRA_DETERMINISTIC, TETRA_TILE(shape), or 0
+ *   flags    TETRA_TILE(shape) or 0; TETRA_EXACT and TETRA_DETERMINISTIC need a workspace and give
+ *            TETRA_ERR_WORKSPACE here (use tetra_dos_forward_ws)
  *   stream   hipStream_t
- * Allocates nothing, except the TETRA_KAHAN buffer described above.
+ * Allocates nothing. Same as tetra_dos_forward_ws with no workspace.
  */
 tetra_status tetra_dos_forward(const tetra_desc* d, const float* eps, const void* w, int wtype,
                                const float* w_scale, float* dos, unsigned flags, void* stream);
+
+/*
+ * Bytes of device workspace tetra_dos_forward_ws needs for these flags: 256 + 8*ne*norb with
+ * TETRA_EXACT or TETRA_DETERMINISTIC (the largest bound exponent, then one 64-bit fixed-point sum
+ * per output element), 0 without them and for invalid arguments.
+ */
+size_t tetra_dos_forward_workspace(const tetra_desc* d, unsigned flags);
+
+/*
+ * tetra_dos_forward with a caller-owned workspace for the exact accumulation (TETRA_EXACT,
+ * TETRA_DETERMINISTIC): device memory of at least tetra_dos_forward_workspace(d, flags) bytes,
+ * 16-byte aligned (TETRA_ERR_ARG otherwise), contents ignored and overwritten, not to be used by
+ * anything else until the work on the stream ends. Without those flags the workspace is not used
+ * and may be NULL; with them a missing or short workspace gives TETRA_ERR_WORKSPACE. The exact
+ * path is four launches (set-up, bound pass, main pass, conversion), all plain kernels, so a call
+ * can be captured in a HIP graph. Allocates nothing.
+ */
+tetra_status tetra_dos_forward_ws(const tetra_desc* d, const float* eps, const void* w, int wtype,
+                                  const float* w_scale, float* dos, unsigned flags, void* workspace,
+                                  size_t ws_bytes, void* stream);
 
 /*
  * Adjoint of tetra_dos_forward for a scalar loss L with G = dL/dDOS (not in the paper; the
@@ -119,9 +144,10 @@ tetra_status tetra_dos_forward(const tetra_desc* d, const float* eps, const void
  *                                           overwritten; may be NULL. For TETRA_W_C32 it is
  *                                           float [nb][norb][nk][2]: dL/d(re a), dL/d(im a)
  *                                           = 2 (re a, im a) dL/db, interleaved like the input
- *   flags     TETRA_TILE(shape) or 0; TETRA_KAHAN is accepted and ignored (each output element sums at
- *             most eight partial values); TETRA_DETERMINISTIC gives TETRA_ERR_UNSUPPORTED (points on
- *             the boundary of a tile are summed with global float atomics, in no fixed order)
+ *   flags     TETRA_TILE(shape) or 0; TETRA_EXACT is accepted and ignored (each output element sums at
+ *             most eight partial values); TETRA_DETERMINISTIC gives TETRA_ERR_UNSUPPORTED here (points
+ *             on the boundary of a tile are summed with global float atomics, in no fixed order; the
+ *             two-phase output of tetra_dos_backward_ws is deterministic)
  * At least one of grad_eps, grad_w must be non-NULL. Where an energy E_j equals a corner energy the
  * loss is not differentiable; the one-sided value of the case containing E_j is returned.
  * Allocates nothing. Same as tetra_dos_backward_ws with no workspace.
@@ -162,7 +188,7 @@ tetra_status tetra_dos_backward_ws(const tetra_desc* d, const float* eps, const 
  *
  * with w_l = 0 for E_j <= E1 and w_l = V_T/(4 V_G) for E_j >= E4, so nos[j][m] counts the states of
  * orbital m up to E_j per k-point (unit cell). Arguments as for tetra_dos_forward; nos is device
- * float [ne][norb], overwritten. flags: TETRA_TILE(shape) or 0 (TETRA_KAHAN and TETRA_DETERMINISTIC
+ * float [ne][norb], overwritten. flags: TETRA_TILE(shape) or 0 (TETRA_EXACT and TETRA_DETERMINISTIC
  * give TETRA_ERR_UNSUPPORTED). The kernels add the increments of each tetrahedron-band's weights
  * between neighbouring grid energies; the weights are evaluated in FP32, or in FP64 on the tiles
  * where a tetrahedron spans more than 64 energy steps (FP32 increments there would lose about
@@ -210,21 +236,26 @@ size_t tetra_dos_batched_workspace(const tetra_item* items, int n, int wtype, un
  * and not used by anything else until the work on `stream` completes. Each item's dos is
  * overwritten. Every item uses weight type wtype (with its own w_scale for TETRA_W_F16).
  * Allocates nothing and copies nothing to the device, so a call can be captured in a HIP graph.
- * flags must be 0 (TETRA_KAHAN and TETRA_DETERMINISTIC are not supported here:
+ * flags must be 0 (TETRA_EXACT and TETRA_DETERMINISTIC are not supported here:
  * TETRA_ERR_UNSUPPORTED).
  */
 tetra_status tetra_dos_batched(const tetra_item* items, int n, int wtype, unsigned flags,
                                void* workspace, size_t ws_bytes, void* stream);
 
 /*
- * Measurement helper, not part of the DOS computation: `blocks` workgroups of 256 lanes, each lane
- * issuing `iters` x 4 64-bit LDS atomic adds to a word of its own (no two adds of one instruction to
- * the same address): the best case of the kernels' histogram deposits. Timed on `stream`, it gives
- * the device's rate of LDS atomics, a ceiling for the deposit-bound part of the forward kernel.
- *   out      device, uint64 [blocks], overwritten (one checksum per workgroup)
- * blocks in 1..2^24, iters in 1..2^24. Allocates nothing.
+ * FP16 storage of orbital weights with a per-band power-of-two scale (the input format of
+ * TETRA_W_F16; the precision variant's storage, not in the paper, which is FP32 throughout):
+ *   w_scale[n] = 2^e_n, e_n = ceil(log2 max_{m,k} |w[n][m][k]|) clamped to [-126, 126], e_n = 0 for
+ *                an all-zero band (e_n from the exponent and mantissa fields of that maximum);
+ *   w16[n][m][k] = w[n][m][k] / w_scale[n] rounded to the nearest FP16 value (ties to even).
+ * The division by a power of two is exact, so the only error is the FP16 rounding.
+ *   w        device, float [nb][norb][nk]  input weights (finite; other values are unspecified)
+ *   w16      device, FP16 [nb][norb][nk]   output, overwritten
+ *   w_scale  device, float [nb]            output, overwritten (used as scratch until the last launch)
+ * nb, norb, nk >= 1 and nb*norb*nk < 2^31 (TETRA_ERR_ARG otherwise). Four launches on `stream`;
+ * allocates nothing.
  */
-tetra_status tetra_probe_lds_atomics(int blocks, int iters, unsigned long long* out, void* stream);
+tetra_status tetra_pack_f16(int nb, int norb, int nk, const float* w, void* w16, float* w_scale, void* stream);
 
 /* Static text for a status code. */
 const char* tetra_status_string(int status);

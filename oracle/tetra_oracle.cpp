@@ -376,9 +376,11 @@ int tetra_oracle_nos(int n1, int n2, int n3, int nb, int norb, double e0, double
 // Gradient of a scalar loss L(DOS) given G[j][m] = dL/dDOS[j][m]:
 //   grad_w[n][m][k]  = dL/db[n][m][k]   (exact: DOS is linear in b)
 //   grad_eps[n][k]   = dL/deps[n][k]    (through the sorted corner energies, mapped back to corners)
-// Either output may be NULL; both are overwritten (FP64, host memory). Bands are independent, so
-// the work is split over bands and every output element is summed in a fixed order.
-// Returns 0, or -1 on invalid arguments.
+// Either output may be NULL; both are overwritten (FP64, host memory). The work is split over
+// (band, slab of constant i1) tasks. A slab's cubes touch the k-points of planes i1 and i1 + 1, so
+// the slabs run in phases (even i1, odd i1, and the last slab on its own when n1 is odd) in which no
+// two tasks touch the same output element: every element is summed in the same order whatever the
+// thread count. Returns 0, or -1 on invalid arguments.
 int tetra_oracle_dos_backward(int n1, int n2, int n3, int nb, int norb, double e0, double de, int ne,
                               const float* eps, const float* w, const double* G, double* grad_eps,
                               double* grad_w, int nthreads) {
@@ -390,11 +392,24 @@ int tetra_oracle_dos_backward(int n1, int n2, int n3, int nb, int norb, double e
   if (grad_w) std::fill(grad_w, grad_w + (size_t)nb * norb * nk, 0.0);
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+  const bool odd = n1 > 1 && (n1 % 2) == 1;
+  const int last = odd ? n1 - 1 : n1;  // slabs below `last` go by parity, the odd last one alone
+  for (int phase = 0; phase < (odd ? 3 : 2); ++phase) {
+    std::vector<int> slabs;
+    if (phase < 2) {
+      for (int i1 = phase; i1 < last; i1 += 2) slabs.push_back(i1);
+    } else {
+      slabs.push_back(n1 - 1);
+    }
+    const int ntask = nb * (int)slabs.size();
+#ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 1)
 #endif
-  for (int n = 0; n < nb; ++n) {
-    std::vector<double> gb(4 * (size_t)norb), s(4);
-    for (int i1 = 0; i1 < n1; ++i1)
+    for (int task = 0; task < ntask; ++task) {
+      const int n = task / (int)slabs.size();
+      const int i1 = slabs[task % slabs.size()];
+      std::vector<double> gb(4 * (size_t)norb);
       for (int i2 = 0; i2 < n2; ++i2)
         for (int i3 = 0; i3 < n3; ++i3)
           for (int t = 0; t < 6; ++t) {
@@ -434,6 +449,7 @@ int tetra_oracle_dos_backward(int n1, int n2, int n3, int nb, int norb, double e
                 for (int m = 0; m < norb; ++m) grad_w[((int64_t)n * norb + m) * nk + k] += gb[(size_t)l * norb + m];
             }
           }
+    }
   }
   return 0;
 }

@@ -15,7 +15,8 @@ import os
 
 __all__ = [
     "TetraError",
-    "TETRA_KAHAN",
+    "TETRA_EXACT",
+    "TETRA_DETERMINISTIC",
     "TETRA_W_F32",
     "TETRA_W_F16",
     "TETRA_W_C32",
@@ -23,6 +24,7 @@ __all__ = [
     "lib",
     "make_desc",
     "dos_forward",
+    "forward_workspace_bytes",
     "dos_backward",
     "backward_workspace_bytes",
     "nos_forward",
@@ -41,7 +43,7 @@ TETRA_OK = 0
 TETRA_W_F32 = 0
 TETRA_W_F16 = 1
 TETRA_W_C32 = 2
-TETRA_KAHAN = 1
+TETRA_EXACT = 1
 TETRA_DETERMINISTIC = 2
 MAX_NORB = 16
 # tile shapes (cubes along grid axes 1, 2, 3) selectable through the flags' bits 8..11
@@ -107,6 +109,12 @@ def lib():
         p, i, u = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint
         L.tetra_dos_forward.argtypes = [ctypes.POINTER(TetraDesc), p, p, i, p, p, u, p]
         L.tetra_dos_forward.restype = i
+        L.tetra_dos_forward_workspace.argtypes = [ctypes.POINTER(TetraDesc), u]
+        L.tetra_dos_forward_workspace.restype = ctypes.c_size_t
+        L.tetra_dos_forward_ws.argtypes = [ctypes.POINTER(TetraDesc), p, p, i, p, p, u, p, ctypes.c_size_t, p]
+        L.tetra_dos_forward_ws.restype = i
+        L.tetra_pack_f16.argtypes = [i, i, i, p, p, p, p]
+        L.tetra_pack_f16.restype = i
         L.tetra_nos_forward.argtypes = [ctypes.POINTER(TetraDesc), p, p, i, p, p, u, p]
         L.tetra_nos_forward.restype = i
         L.tetra_dos_binned.argtypes = [ctypes.POINTER(TetraDesc), p, p, i, p, p, u, p]
@@ -121,8 +129,6 @@ def lib():
         L.tetra_dos_batched_workspace.restype = ctypes.c_size_t
         L.tetra_dos_batched.argtypes = [ctypes.POINTER(TetraItem), i, i, u, p, ctypes.c_size_t, p]
         L.tetra_dos_batched.restype = i
-        L.tetra_probe_lds_atomics.argtypes = [i, i, p, p]
-        L.tetra_probe_lds_atomics.restype = i
         L.tetra_status_string.argtypes = [i]
         L.tetra_status_string.restype = ctypes.c_char_p
         L.tetra_last_hip_error.argtypes = []
@@ -238,14 +244,31 @@ def dos_binned(eps, w, grid, e0, de, ne, *, w_scale=None, out=None, tile=None):
     return _integrated("tetra_dos_binned", eps, w, grid, e0, de, ne, w_scale, out, tile)
 
 
-def dos_forward(eps, w, grid, e0, de, ne, *, w_scale=None, kahan=False, deterministic=False, out=None, tile=None):
+def _check_workspace(workspace, need, dev):
+    if workspace.dtype != _torch().uint8 or workspace.device != dev or workspace.numel() < need \
+            or not workspace.is_contiguous():
+        raise ValueError(f"workspace must be a contiguous uint8 tensor on {dev} of at least {need} bytes")
+
+
+def forward_workspace_bytes(grid, nb, norb, e0, de, ne, *, exact=False, deterministic=False, tile=None):
+    """Device bytes ``dos_forward`` needs for its exact accumulation (0 without ``exact`` or
+    ``deterministic``)."""
+    d = make_desc(grid, nb, norb, e0, de, ne)
+    flags = (TETRA_EXACT if exact else 0) | (TETRA_DETERMINISTIC if deterministic else 0) | _tile_flag(tile)
+    return int(lib().tetra_dos_forward_workspace(ctypes.byref(d), flags))
+
+
+def dos_forward(eps, w, grid, e0, de, ne, *, w_scale=None, exact=False, deterministic=False, out=None, tile=None,
+                workspace=None):
     """Orbital-resolved DOS ``[ne, norb]`` (FP32) on the current HIP stream.
 
     eps: float32 ``[nb, nk]``; w: float32 or float16 orbital weights ``[nb, norb, nk]`` (float16 needs
     ``w_scale`` float32 ``[nb]``), or complex64 amplitudes a (the weights are ``|a|^2``, formed in the
-    kernels); grid: (n1, n2, n3) with nk = n1*n2*n3; E_j = e0 + j*de. ``kahan`` selects the
+    kernels); grid: (n1, n2, n3) with nk = n1*n2*n3; E_j = e0 + j*de. ``exact`` selects the
     exact cross-workgroup accumulation, ``deterministic`` asks for a bitwise reproducible result (the
-    same exact path); ``tile`` an index into ``TILE_SHAPES`` (default 0).
+    same exact path); both use a device workspace (``workspace``, a uint8 tensor of at least
+    ``forward_workspace_bytes`` bytes, or one allocated here). ``tile`` an index into ``TILE_SHAPES``
+    (default 0).
     """
     torch = _torch()
     nk, nb, norb = _shapes(eps, w, grid)
@@ -257,12 +280,19 @@ def dos_forward(eps, w, grid, e0, de, ne, *, w_scale=None, kahan=False, determin
         out = torch.empty((int(ne), norb), dtype=torch.float32, device=dev)
     _require(out, "out", (int(ne), norb), (torch.float32,), dev)
     d = make_desc(grid, nb, norb, e0, de, ne)
-    st = lib().tetra_dos_forward(
+    flags = (TETRA_EXACT if exact else 0) | (TETRA_DETERMINISTIC if deterministic else 0) | _tile_flag(tile)
+    need = int(lib().tetra_dos_forward_workspace(ctypes.byref(d), flags))
+    ws_ptr, ws_bytes = None, 0
+    if need:
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+        _check_workspace(workspace, need, dev)
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel()
+    st = lib().tetra_dos_forward_ws(
         ctypes.byref(d), eps.data_ptr(), w.data_ptr(), wtype,
-        w_scale.data_ptr() if w_scale is not None else None, out.data_ptr(),
-        (TETRA_KAHAN if kahan else 0) | (TETRA_DETERMINISTIC if deterministic else 0) | _tile_flag(tile),
+        w_scale.data_ptr() if w_scale is not None else None, out.data_ptr(), flags, ws_ptr, ws_bytes,
         _stream_handle(dev))
-    _check("tetra_dos_forward", st)
+    _check("tetra_dos_forward_ws", st)
     return out
 
 
@@ -308,9 +338,7 @@ def dos_backward(eps, w, grid, e0, de, grad_dos, *, w_scale=None, need_eps=True,
     if need:
         if workspace is None:
             workspace = torch.empty(need, dtype=torch.uint8, device=dev)
-        elif workspace.dtype != torch.uint8 or workspace.device != dev or workspace.numel() < need \
-                or not workspace.is_contiguous():
-            raise ValueError(f"workspace must be a contiguous uint8 tensor on {dev} of at least {need} bytes")
+        _check_workspace(workspace, need, dev)
         ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel()
     st = lib().tetra_dos_backward_ws(
         ctypes.byref(d), eps.data_ptr(), w.data_ptr(), wtype,
@@ -392,18 +420,23 @@ def _autograd_function():
 
     class _TetraDOS(torch.autograd.Function):
         @staticmethod
-        def forward(ctx, eps, w, grid, e0, de, ne, kahan, tiles):
-            ctx.save_for_backward(eps, w)
+        def forward(ctx, eps, w, grid, e0, de, ne, exact, tiles, w_scale):
+            ctx.save_for_backward(eps, w, w_scale)
             ctx.args = (tuple(grid), float(e0), float(de), tiles[1])
-            return dos_forward(eps.contiguous(), w.contiguous(), grid, e0, de, ne, kahan=kahan, tile=tiles[0])
+            return dos_forward(eps.contiguous(), w.contiguous(), grid, e0, de, ne, w_scale=w_scale, exact=exact,
+                               tile=tiles[0])
 
         @staticmethod
         def backward(ctx, g):
-            eps, w = ctx.saved_tensors
+            eps, w, w_scale = ctx.saved_tensors
             grid, e0, de, btile = ctx.args
-            ge, gw = dos_backward(eps.contiguous(), w.contiguous(), grid, e0, de, g.contiguous(),
-                                  need_eps=ctx.needs_input_grad[0], need_w=ctx.needs_input_grad[1], tile=btile)
-            return ge, gw, None, None, None, None, None, None
+            need_w = ctx.needs_input_grad[1]
+            ge, gw = dos_backward(eps.contiguous(), w.contiguous(), grid, e0, de, g.contiguous(), w_scale=w_scale,
+                                  need_eps=ctx.needs_input_grad[0], need_w=need_w, tile=btile)
+            if gw is not None and w.dtype == _torch().float16:
+                # dL/d(stored FP16 value) = scale_n dL/db (the kernel's gradient is of b = scale_n w16)
+                gw = (gw * w_scale[:, None, None]).to(w.dtype)
+            return ge, gw, None, None, None, None, None, None, None
 
     return _TetraDOS
 
@@ -411,28 +444,18 @@ def _autograd_function():
 _FN = None
 
 
-def dos(eps, w, grid, e0, de, ne, kahan=False, tile=None, backward_tile=None):
-    """Differentiable orbital-resolved DOS ``[ne, norb]`` (float32 weights or complex64 amplitudes).
+def dos(eps, w, grid, e0, de, ne, exact=False, tile=None, backward_tile=None, w_scale=None):
+    """Differentiable orbital-resolved DOS ``[ne, norb]`` (float32 weights, float16 weights with their
+    per-band ``w_scale``, or complex64 amplitudes).
 
-    Gradients with respect to ``eps`` and ``w`` come from the adjoint kernel.
+    Gradients with respect to ``eps`` and ``w`` come from the adjoint kernel. For float16 weights the
+    gradient with respect to ``w`` is that of the stored values (``scale_n dL/db``, rounded to
+    float16); ``w_scale`` itself is treated as a constant.
     """
     global _FN
     if _FN is None:
         _FN = _autograd_function()
-    return _FN.apply(eps, w, tuple(grid), e0, de, ne, kahan, (tile, backward_tile))
-
-
-def probe_lds_atomics(blocks, iters, device=None, out=None):
-    """Measurement helper: launch ``tetra_probe_lds_atomics`` on the current stream (``blocks`` x 256
-    lanes x ``iters`` x 4 conflict-free 64-bit LDS atomic adds); returns the uint64 checksum tensor."""
-    torch = _torch()
-    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-    if out is None:
-        out = torch.empty(int(blocks), dtype=torch.int64, device=dev)
-    _require(out, "out", (int(blocks),), (torch.int64,), dev)
-    _check("tetra_probe_lds_atomics", lib().tetra_probe_lds_atomics(int(blocks), int(iters), out.data_ptr(),
-                                                                     _stream_handle(dev)))
-    return out
+    return _FN.apply(eps, w, tuple(grid), e0, de, ne, exact, (tile, backward_tile), w_scale)
 
 
 def from_eigh(evals, evecs, amplitudes=False):
@@ -451,16 +474,25 @@ def from_eigh(evals, evecs, amplitudes=False):
     return eps, w.permute(2, 1, 0).contiguous().float()
 
 
-def half_weights(w):
-    """FP16 weights with a per-band power-of-two scale: ``(w16 [nb, norb, nk], scale [nb])``.
+def half_weights(w, *, out=None, scale=None):
+    """FP16 weights with a per-band power-of-two scale, by the library's pack kernel
+    (``tetra_pack_f16``): ``(w16 [nb, norb, nk], scale [nb])``.
 
-    scale_n = 2^ceil(log2 max_{m,k} w[n, m, k]) (1 for an all-zero band), w16 = RNE(w / scale_n), so
-    the scaling itself is exact and the only error is FP16 rounding.
+    scale_n = 2^ceil(log2 max_{m,k} |w[n, m, k]|) (clamped to 2^-126..2^126; 1 for an all-zero band),
+    w16 = RNE(w / scale_n), so the scaling itself is exact and the only error is FP16 rounding.
     """
     torch = _torch()
-    mx = w.abs().amax(dim=(1, 2)).double()
-    e = torch.where(mx > 0, torch.ceil(torch.log2(torch.where(mx > 0, mx, torch.ones_like(mx)))),
-                    torch.zeros_like(mx))
-    scale = torch.pow(2.0, e).float()
-    w16 = (w / scale[:, None, None]).to(torch.float16)
-    return w16.contiguous(), scale.contiguous()
+    if w.dim() != 3:
+        raise ValueError("w must be [nb, norb, nk]")
+    nb, norb, nk = (int(x) for x in w.shape)
+    dev = w.device
+    _require(w, "w", (nb, norb, nk), (torch.float32,), dev)
+    if out is None:
+        out = torch.empty((nb, norb, nk), dtype=torch.float16, device=dev)
+    if scale is None:
+        scale = torch.empty(nb, dtype=torch.float32, device=dev)
+    _require(out, "out", (nb, norb, nk), (torch.float16,), dev)
+    _require(scale, "scale", (nb,), (torch.float32,), dev)
+    _check("tetra_pack_f16", lib().tetra_pack_f16(nb, norb, nk, w.data_ptr(), out.data_ptr(), scale.data_ptr(),
+                                                  _stream_handle(dev)))
+    return out, scale

@@ -1,6 +1,7 @@
-"""Build ``libtetra.so`` (the C-ABI library) in-tree with hipcc for gfx950.
+"""Build ``libtetra.so`` (the C-ABI library) in-tree with hipcc for gfx950, and the benchmark's
+measurement helper ``libtetra_probe.so`` (not part of the DOS library).
 
-Each HIP source is compiled to an object in parallel, then the objects are linked.
+Each HIP source is compiled to an object in parallel, then each library's objects are linked.
 """
 from __future__ import annotations
 
@@ -16,6 +17,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libtetra.so")
+PROBE_LIB = os.path.join(PKG, "libtetra_probe.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -35,6 +37,10 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
+def probe_sources():
+    return sorted(glob.glob(os.path.join(CSRC, "probe", "*.hip")))
+
+
 def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -45,19 +51,22 @@ def _run(cmd, verbose):
 
 
 def build(extra_flags=(), verbose: bool = False) -> str:
-    """Compile every HIP source into ``paper_1710_10789_amd/libtetra.so``; returns its path."""
+    """Compile every HIP source into ``paper_1710_10789_amd/libtetra.so`` (and the probe sources into
+    ``libtetra_probe.so``); returns the DOS library's path."""
     with tempfile.TemporaryDirectory(prefix="tetra_build_") as tmpdir:
-        objs = []
+        libs = {LIB: [], PROBE_LIB: []}
         cmds = []
-        for src in sources():
-            obj = os.path.join(tmpdir, os.path.basename(src) + ".o")
-            objs.append(obj)
-            cmds.append([HIPCC, *FLAGS, *extra_flags, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj])
+        for lib, srcs in ((LIB, sources()), (PROBE_LIB, probe_sources())):
+            for src in srcs:
+                obj = os.path.join(tmpdir, os.path.basename(src) + ".o")
+                libs[lib].append(obj)
+                cmds.append([HIPCC, *FLAGS, *extra_flags, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj])
         with ThreadPoolExecutor(max_workers=min(len(cmds), max(1, os.cpu_count() or 1))) as ex:
             list(ex.map(lambda c: _run(c, verbose), cmds))
-        tmp = LIB + f".tmp{os.getpid()}"
-        _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
-        os.replace(tmp, LIB)
+        for lib, objs in libs.items():
+            tmp = lib + f".tmp{os.getpid()}"
+            _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
+            os.replace(tmp, lib)
     return LIB
 
 

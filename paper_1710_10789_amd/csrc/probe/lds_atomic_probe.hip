@@ -1,13 +1,12 @@
-// Measurement helper: the throughput of 64-bit integer LDS atomics on gfx950, the instruction the
+// Benchmark-only measurement helper, built into its own library (libtetra_probe.so) and not part of
+// the DOS library or its C ABI: the throughput of 64-bit integer LDS atomics on gfx950, the instruction the
 // forward and number-of-states kernels deposit with. Every lane adds to its own 64-bit word (a lane's
 // word index is its lane number plus a multiple of 64, so the 64 lanes of a wavefront touch 64
 // different words and no two adds of one instruction go to the same address). That is the best case
 // of the histogram deposits, whose lanes may share bins; its rate bounds how fast a kernel that
 // issues a given number of LDS atomics can be.
 
-#include "tetra_probe.h"
-
-namespace tetra {
+#include <hip/hip_runtime.h>
 
 namespace {
 
@@ -41,9 +40,12 @@ __global__ __launch_bounds__(kProbeThreads) void lds_atomic_probe_kernel(unsigne
 
 }  // namespace
 
-hipError_t probe_lds_atomics(int blocks, int iters, unsigned long long* out, hipStream_t s) {
-  hipLaunchKernelGGL(lds_atomic_probe_kernel, dim3(blocks), dim3(kProbeThreads), 0, s, out, iters);
-  return hipGetLastError();
+// `blocks` workgroups of 256 lanes, each lane issuing `iters` x 4 64-bit LDS atomic adds to a word of
+// its own; out (device, uint64 [blocks]) receives one checksum per workgroup, overwritten.
+// Returns 0, -1 for invalid arguments (blocks or iters outside 1..2^24, out NULL), -4 for a failed
+// launch. Asynchronous on `stream`; allocates nothing.
+extern "C" int tetra_probe_lds_atomics(int blocks, int iters, unsigned long long* out, void* stream) {
+  if (!out || blocks < 1 || blocks > (1 << 24) || iters < 1 || iters > (1 << 24)) return -1;
+  hipLaunchKernelGGL(lds_atomic_probe_kernel, dim3(blocks), dim3(kProbeThreads), 0, (hipStream_t)stream, out, iters);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
 }
-
-}  // namespace tetra

@@ -3,11 +3,9 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
-#include <mutex>
 #include <vector>
 
 #include "tetra_internal.h"
-#include "tetra_probe.h"
 
 namespace {
 
@@ -18,39 +16,6 @@ tetra_status hip_status(hipError_t e) {
   std::strncpy(g_last_hip_error, hipGetErrorString(e), sizeof(g_last_hip_error) - 1);
   g_last_hip_error[sizeof(g_last_hip_error) - 1] = '\0';
   return TETRA_ERR_HIP;
-}
-
-// Library-owned scratch for the exact (TETRA_KAHAN) forward: one buffer per device, allocated on first
-// use and grown when a larger problem needs it; kept until the process ends. Calls with TETRA_KAHAN
-// that overlap on one device race on it.
-struct DeviceScratch {
-  void* ptr = nullptr;
-  size_t bytes = 0;
-};
-std::mutex g_scratch_mu;
-std::vector<DeviceScratch> g_scratch;
-
-hipError_t exact_scratch(size_t bytes, void** out) {
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  std::lock_guard<std::mutex> lock(g_scratch_mu);
-  if ((int)g_scratch.size() <= dev) g_scratch.resize(dev + 1);
-  DeviceScratch& s = g_scratch[dev];
-  if (s.bytes < bytes) {
-    if (s.ptr) {
-      e = hipFree(s.ptr);  // waits for work that may still use it
-      if (e != hipSuccess) return e;
-      s.ptr = nullptr;
-      s.bytes = 0;
-    }
-    const size_t want = bytes < (1u << 20) ? (1u << 20) : bytes;
-    e = hipMalloc(&s.ptr, want);
-    if (e != hipSuccess) return e;
-    s.bytes = want;
-  }
-  *out = s.ptr;
-  return hipSuccess;
 }
 
 // Shape and range checks shared by every entry point (no HIP call).
@@ -80,25 +45,40 @@ const float* scale_of(int wtype, const float* w_scale) { return wtype == TETRA_W
 
 extern "C" {
 
-tetra_status tetra_dos_forward(const tetra_desc* d, const float* eps, const void* w, int wtype,
-                               const float* w_scale, float* dos, unsigned flags, void* stream) {
+size_t tetra_dos_forward_workspace(const tetra_desc* d, unsigned flags) {
+  if (check_desc(d) != TETRA_OK) return 0;
+  if (flags & ~(unsigned)(TETRA_EXACT | TETRA_DETERMINISTIC | TETRA_TILE_MASK)) return 0;
+  if ((int)((flags & TETRA_TILE_MASK) >> 8) >= tetra::kTileShapes) return 0;
+  return (flags & (TETRA_EXACT | TETRA_DETERMINISTIC)) ? tetra::forward_exact_scratch_bytes(*d) : 0;
+}
+
+tetra_status tetra_dos_forward_ws(const tetra_desc* d, const float* eps, const void* w, int wtype,
+                                  const float* w_scale, float* dos, unsigned flags, void* workspace,
+                                  size_t ws_bytes, void* stream) {
   tetra_status st = check_desc(d);
   if (st != TETRA_OK) return st;
   if (!eps || !w || !dos) return TETRA_ERR_ARG;
   if ((st = check_weights(wtype, w_scale)) != TETRA_OK) return st;
-  if (flags & ~(unsigned)(TETRA_KAHAN | TETRA_DETERMINISTIC | TETRA_TILE_MASK)) return TETRA_ERR_ARG;
+  if (flags & ~(unsigned)(TETRA_EXACT | TETRA_DETERMINISTIC | TETRA_TILE_MASK)) return TETRA_ERR_ARG;
   const int shape = (int)((flags & TETRA_TILE_MASK) >> 8);
   if (shape >= tetra::kTileShapes) return TETRA_ERR_ARG;
-  // the exact accumulation is also the deterministic one
-  const bool exact = (flags & (TETRA_KAHAN | TETRA_DETERMINISTIC)) != 0;
-  if (exact && shape != 0) return TETRA_ERR_UNSUPPORTED;
-  void* scratch = nullptr;
-  if (exact) {
-    const hipError_t e = exact_scratch(tetra::forward_exact_scratch_bytes(*d), &scratch);
-    if (e != hipSuccess) return hip_status(e);
-  }
-  return hip_status(
-      tetra::forward(*d, eps, w, wtype, scale_of(wtype, w_scale), dos, scratch, shape, (hipStream_t)stream));
+  if (reinterpret_cast<uintptr_t>(workspace) % 16 != 0) return TETRA_ERR_ARG;
+  // the exact accumulation is also the deterministic one; only it uses the workspace
+  const bool exact = (flags & (TETRA_EXACT | TETRA_DETERMINISTIC)) != 0;
+  if (exact && (!workspace || ws_bytes < tetra::forward_exact_scratch_bytes(*d))) return TETRA_ERR_WORKSPACE;
+  return hip_status(tetra::forward(*d, eps, w, wtype, scale_of(wtype, w_scale), dos, exact ? workspace : nullptr,
+                                   shape, (hipStream_t)stream));
+}
+
+tetra_status tetra_dos_forward(const tetra_desc* d, const float* eps, const void* w, int wtype,
+                               const float* w_scale, float* dos, unsigned flags, void* stream) {
+  return tetra_dos_forward_ws(d, eps, w, wtype, w_scale, dos, flags, nullptr, 0, stream);
+}
+
+tetra_status tetra_pack_f16(int nb, int norb, int nk, const float* w, void* w16, float* w_scale, void* stream) {
+  if (nb < 1 || norb < 1 || nk < 1 || !w || !w16 || !w_scale) return TETRA_ERR_ARG;
+  if ((double)nb * norb * nk >= 2147483648.0) return TETRA_ERR_ARG;
+  return hip_status(tetra::pack_f16(nb, (int64_t)norb * nk, w, w16, w_scale, (hipStream_t)stream));
 }
 
 tetra_status tetra_dos_backward_ws(const tetra_desc* d, const float* eps, const void* w, int wtype,
@@ -108,7 +88,7 @@ tetra_status tetra_dos_backward_ws(const tetra_desc* d, const float* eps, const 
   if (st != TETRA_OK) return st;
   if (!eps || !w || !grad_dos || (!grad_eps && !grad_w)) return TETRA_ERR_ARG;
   if ((st = check_weights(wtype, w_scale)) != TETRA_OK) return st;
-  if (flags & ~(unsigned)(TETRA_KAHAN | TETRA_DETERMINISTIC | TETRA_TILE_MASK)) return TETRA_ERR_ARG;
+  if (flags & ~(unsigned)(TETRA_EXACT | TETRA_DETERMINISTIC | TETRA_TILE_MASK)) return TETRA_ERR_ARG;
   const int shape = (int)((flags & TETRA_TILE_MASK) >> 8);
   if (shape >= tetra::kTileShapes) return TETRA_ERR_ARG;
   const size_t need = tetra::backward_workspace_bytes(*d, shape);
@@ -128,7 +108,7 @@ tetra_status tetra_dos_backward(const tetra_desc* d, const float* eps, const voi
 
 size_t tetra_dos_backward_workspace(const tetra_desc* d, unsigned flags) {
   if (check_desc(d) != TETRA_OK) return 0;
-  if (flags & ~(unsigned)(TETRA_KAHAN | TETRA_DETERMINISTIC | TETRA_TILE_MASK)) return 0;
+  if (flags & ~(unsigned)(TETRA_EXACT | TETRA_DETERMINISTIC | TETRA_TILE_MASK)) return 0;
   const int shape = (int)((flags & TETRA_TILE_MASK) >> 8);
   if (shape >= tetra::kTileShapes) return 0;
   return tetra::backward_workspace_bytes(*d, shape);
@@ -142,10 +122,10 @@ tetra_status nos_entry(const tetra_desc* d, const float* eps, const void* w, int
   if (st != TETRA_OK) return st;
   if (!eps || !w || !out) return TETRA_ERR_ARG;
   if ((st = check_weights(wtype, w_scale)) != TETRA_OK) return st;
-  if (flags & ~(unsigned)(TETRA_KAHAN | TETRA_DETERMINISTIC | TETRA_TILE_MASK)) return TETRA_ERR_ARG;
+  if (flags & ~(unsigned)(TETRA_EXACT | TETRA_DETERMINISTIC | TETRA_TILE_MASK)) return TETRA_ERR_ARG;
   const int shape = (int)((flags & TETRA_TILE_MASK) >> 8);
   if (shape >= tetra::kTileShapes) return TETRA_ERR_ARG;
-  if (flags & (TETRA_KAHAN | TETRA_DETERMINISTIC)) return TETRA_ERR_UNSUPPORTED;
+  if (flags & (TETRA_EXACT | TETRA_DETERMINISTIC)) return TETRA_ERR_UNSUPPORTED;
   return hip_status(tetra::nos(*d, eps, w, wtype, scale_of(wtype, w_scale), out, binned, shape, (hipStream_t)stream));
 }
 
@@ -173,7 +153,7 @@ tetra_status tetra_dos_batched(const tetra_item* items, int n, int wtype, unsign
                                size_t ws_bytes, void* stream) {
   if (!items || n < 1) return TETRA_ERR_ARG;
   if (wtype != TETRA_W_F32 && wtype != TETRA_W_F16 && wtype != TETRA_W_C32) return TETRA_ERR_ARG;
-  if (flags & ~(unsigned)(TETRA_KAHAN | TETRA_DETERMINISTIC)) return TETRA_ERR_ARG;
+  if (flags & ~(unsigned)(TETRA_EXACT | TETRA_DETERMINISTIC)) return TETRA_ERR_ARG;
   for (int i = 0; i < n; ++i) {
     const tetra_item& it = items[i];
     const tetra_status st = check_desc(&it.d);
@@ -182,16 +162,11 @@ tetra_status tetra_dos_batched(const tetra_item* items, int n, int wtype, unsign
     if (check_weights(wtype, it.w_scale) != TETRA_OK) return TETRA_ERR_ARG;
     if (it.tile < 0 || it.tile >= tetra::kTileShapes) return TETRA_ERR_ARG;
   }
-  if (flags & (TETRA_KAHAN | TETRA_DETERMINISTIC)) return TETRA_ERR_UNSUPPORTED;
+  if (flags & (TETRA_EXACT | TETRA_DETERMINISTIC)) return TETRA_ERR_UNSUPPORTED;
   if (!workspace || ws_bytes < 256 * tetra::batched_launches(items, n)) return TETRA_ERR_WORKSPACE;
   std::vector<int> shapes(n);
   for (int i = 0; i < n; ++i) shapes[i] = items[i].tile;
   return hip_status(tetra::batched(items, shapes.data(), n, wtype, workspace, (hipStream_t)stream));
-}
-
-tetra_status tetra_probe_lds_atomics(int blocks, int iters, unsigned long long* out, void* stream) {
-  if (!out || blocks < 1 || blocks > (1 << 24) || iters < 1 || iters > (1 << 24)) return TETRA_ERR_ARG;
-  return hip_status(tetra::probe_lds_atomics(blocks, iters, out, (hipStream_t)stream));
 }
 
 const char* tetra_status_string(int status) {

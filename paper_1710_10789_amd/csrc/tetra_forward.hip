@@ -49,8 +49,9 @@ struct FwdArgs {
   const void* w;        // float, _Float16 or float2 (complex amplitude) [nb][norb][nk]
   const float* w_scale;  // per-band scale of _Float16 weights
   float* dos;
-  float* gbound;                // exact mode: sum of the per-workgroup bounds (accumulated in mode 1)
-  unsigned long long* gacc;     // exact mode: [ne][norb] 64-bit fixed-point sums (mode 2)
+  int* gexp;                 // exact mode: largest bound exponent of any workgroup (atomicMax in mode 1)
+  unsigned long long* gacc;  // exact mode: [ne][norb] sums in the common 64-bit fixed point (mode 2)
+  int lg_units;              // exact mode: ceil(log2(nunits))
   int wtype;  // TETRA_W_* of w
   int n1, n2, n3, ne;
   float e0, de, inv_de, V;
@@ -81,9 +82,19 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
+// Common fixed point of the exact mode: with E the largest bound exponent of any workgroup (each
+// workgroup's bins sum to at most 2^E in magnitude) and L = ceil(log2(workgroups)), the total of any
+// bin is below 2^(E + L), so the scale 2^(62 - E - L) keeps every partial and total sum of the
+// 64-bit two's-complement accumulator in range.
+__device__ __forceinline__ int exact_scale_exp(int gexp, int lg_units) { return 62 - gexp - lg_units; }
+
 // One work unit (tile, band) of the forward pass; every lane of the workgroup calls it.
-// MODE 0: DOS with per-workgroup scales; 1: only add this workgroup's bound to *gbound;
-// 2: DOS in the common scale fixed by *gbound, summed exactly into gacc with 64-bit global atomics.
+// MODE 0: DOS with per-workgroup scales, flushed with float atomics;
+// 1: only the workgroup's bound exponent, into *gexp (atomicMax: independent of the order);
+// 2: DOS with per-workgroup scales as in mode 0; each bin's exact per-workgroup sum is rounded once
+//    to the common fixed point fixed by *gexp and added to gacc with a 64-bit integer atomic. Both
+//    steps are independent of the order in which workgroups run, so the result is bitwise
+//    reproducible.
 template <int NORB, typename WT, int MODE>
 __device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
   constexpr int NPAIR = (NORB + 1) / 2;
@@ -162,7 +173,7 @@ __device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
   // Bound on any bin's sum: sum over tetrahedra with a possibly non-empty window of 12 V bmax / E41.
   float bound = 0.0f, narrow = 0.0f;
   const float c12 = 12.0f * a.V * bmax;
-  if (MODE != 2 && valid) {
+  if (valid) {
 #pragma unroll 1
     for (int t = 0; t < 6; ++t) {
       const uint32_t slots = tet_slots(t);
@@ -198,13 +209,16 @@ __device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
     B += s_red[i];
     Bn += s_red[NT / 64 + i];
   }
+  if (!(B > 0.0f)) return;  // nothing to add (uniform across the block)
   if (MODE == 1) {
-    if (tid == 0 && B > 0.0f) atomic_add_global(a.gbound, B);
+    if (tid == 0) {
+      int be;
+      frexpf(fminf(B, 3.0e38f), &be);
+      atomicMax(a.gexp, be);
+    }
     return;
   }
-  if (MODE == 2) B = 1.0001f * *a.gbound;  // margin for the rounding of the float sum
-  if (!(B > 0.0f)) return;  // nothing to add (uniform across the block)
-  const bool packed = MODE == 0 && bmin >= 0.0f && Bn <= 0.5f * B;  // uniform across the block
+  const bool packed = bmin >= 0.0f && Bn <= 0.5f * B;  // uniform across the block
   const int rows = packed ? NPAIR : NORB;
   const int RS = packed ? RSP : RSW;
   // Copies: lane l adds into copy l % CP of a bin (each bin's copies are adjacent words), so the lanes
@@ -219,6 +233,8 @@ __device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
   const int sexp = min((packed ? 30 : 62) - bexp, 126);
   const float S = ldexpf(1.0f, sexp);  // B * S <= 2^30 (packed) or 2^62
   const double inv_S = ldexp(1.0, -sexp);
+  // exact mode: shift from this workgroup's fixed point to the common one (negative: to the right)
+  const int dshift = MODE == 2 ? exact_scale_exp(*a.gexp, a.lg_units) - sexp : 0;
   // Fold the power-of-two scale into the staged weights (exact): every deposit is then an integer-valued
   // float without a per-orbital multiply.
   for (int q = tid; q < NP * NORB; q += NT) s_w[q] *= S;
@@ -319,9 +335,18 @@ __device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
       const int row = packed ? (m >> 1) : m;
       const unsigned long long* hw = &s_hist[row * RS + (r << cpl)];
       if (MODE == 2) {
-        unsigned long long w = 0ull;
-        for (int c = 0; c < CP; ++c) w += hw[c];
-        if (w != 0ull) atomicAdd(&a.gacc[(int64_t)(c0 + r) * NORB + m], w);
+        // exact sum of the copies in this workgroup's fixed point (|v| <= B S <= 2^62), then one
+        // rounding (halves up) to the common fixed point
+        long long v = 0;
+        for (int c = 0; c < CP; ++c) {
+          const unsigned long long w = hw[c];
+          v += packed ? (long long)(unsigned)((m & 1) ? (w >> 32) : (w & 0xffffffffull)) : (long long)w;
+        }
+        long long q;
+        if (dshift >= 0) q = (long long)((unsigned long long)v << dshift);
+        else if (dshift > -63) q = (v + (1ll << (-dshift - 1))) >> (-dshift);
+        else q = 0;  // |v| < 2^62 <= half a unit of the common fixed point
+        if (q != 0) atomicAdd(&a.gacc[(int64_t)(c0 + r) * NORB + m], (unsigned long long)q);
       } else {
         double sum = 0.0;
         for (int c = 0; c < CP; ++c) {
@@ -390,8 +415,9 @@ __global__ __launch_bounds__(NT, NORB <= 8 ? 5 : 2) void dos_batched_kernel(Batc
     a.w_scale = it.w_scale;
     a.wtype = 0;  // not read by the unit body (the type is the template argument)
     a.dos = it.dos;
-    a.gbound = nullptr;
+    a.gexp = nullptr;
     a.gacc = nullptr;
+    a.lg_units = 0;
     a.n1 = it.n1;
     a.n2 = it.n2;
     a.n3 = it.n3;
@@ -474,20 +500,20 @@ hipError_t launch_fwd_mode(const FwdArgs& a, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
-__global__ void fill_zero_u64_kernel(unsigned long long* p, int64_t n) {
+constexpr int kNoBound = -100000;  // *gexp before any workgroup has a bound
+
+// Exact-mode set-up: no bound yet, every accumulator at zero (plain stores: capturable in a graph).
+__global__ void exact_init_kernel(int* gexp, unsigned long long* acc, int64_t n) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *gexp = kNoBound;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = 0ull;
+    acc[i] = 0ull;
 }
 
-// dos = gacc / S with S the common scale of mode 2.
-__global__ void fixed_to_float_kernel(const unsigned long long* acc, const float* gbound, float* dos, int64_t n) {
-  const float B = 1.0001f * *gbound;
-  double inv_S = 0.0;
-  if (B > 0.0f) {
-    int bexp;
-    frexpf(fminf(B, 3.0e38f), &bexp);
-    inv_S = ldexp(1.0, -min(62 - bexp, 126));
-  }
+// dos = acc / S with S the common scale of mode 2 (all zero when no workgroup had anything to add).
+__global__ void fixed_to_float_kernel(const unsigned long long* acc, const int* gexp, int lg_units, float* dos,
+                                      int64_t n) {
+  const int ge = *gexp;
+  const double inv_S = ge == kNoBound ? 0.0 : ldexp(1.0, -exact_scale_exp(ge, lg_units));
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     dos[i] = (float)((double)(long long)acc[i] * inv_S);
 }
@@ -501,7 +527,7 @@ hipError_t launch_fwd(const FwdArgs& a, int grid, hipStream_t s) {
   if (e != hipSuccess) return e;
   const int64_t n = (int64_t)a.ne * NORB;
   hipLaunchKernelGGL(fixed_to_float_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, s,
-                     a.gacc, a.gbound, a.dos, n);
+                     a.gacc, a.gexp, a.lg_units, a.dos, n);
   return hipGetLastError();
 }
 
@@ -518,8 +544,8 @@ hipError_t forward(const tetra_desc& d, const float* eps, const void* w, int wty
                    void* exact_scratch, int shape, hipStream_t s) {
   FwdArgs a;
   a.wtype = wtype;
-  // exact_scratch (exact mode): 256 bytes holding the bound, then ne*norb 64-bit sums
-  a.gbound = exact_scratch ? static_cast<float*>(exact_scratch) : nullptr;
+  // exact_scratch (exact mode): 256 bytes holding the largest bound exponent, then ne*norb 64-bit sums
+  a.gexp = exact_scratch ? static_cast<int*>(exact_scratch) : nullptr;
   a.gacc = exact_scratch ? reinterpret_cast<unsigned long long*>(static_cast<char*>(exact_scratch) + 256) : nullptr;
   a.eps = eps;
   a.w = w;
@@ -543,14 +569,14 @@ hipError_t forward(const tetra_desc& d, const float* eps, const void* w, int wty
   a.ntiles = a.t1 * a.t2 * a.t3;
   a.nunits = a.ntiles * d.nb;
   a.per_xcd = (a.nunits + NXCD - 1) / NXCD;
+  a.lg_units = 0;
+  while ((1ll << a.lg_units) < (long long)a.nunits) ++a.lg_units;
   const int grid = a.per_xcd * NXCD;
   hipError_t e = hipSuccess;
   if (exact_scratch) {
-    e = fill_zero(a.gbound, 1, s);
-    if (e != hipSuccess) return e;
     const int64_t n = (int64_t)d.ne * d.norb;
-    hipLaunchKernelGGL(fill_zero_u64_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, s,
-                       a.gacc, n);
+    hipLaunchKernelGGL(exact_init_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, s,
+                       a.gexp, a.gacc, n);
     e = hipGetLastError();
   } else {
     e = fill_zero(dos, (int64_t)d.ne * d.norb, s);

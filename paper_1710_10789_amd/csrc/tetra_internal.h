@@ -35,7 +35,10 @@ hipError_t forward(const tetra_desc& d, const float* eps, const void* w, int wty
 // workspace holds one 256-byte work counter per launch.
 size_t batched_launches(const tetra_item* items, int n);
 hipError_t batched(const tetra_item* items, const int* shapes, int n, int wtype, void* workspace, hipStream_t s);
+// Exact mode of the forward: 256 bytes (the largest bound exponent), then ne*norb 64-bit sums.
 inline size_t forward_exact_scratch_bytes(const tetra_desc& d) { return 256 + 8 * (size_t)d.ne * d.norb; }
+// FP16 weights with a per-band power-of-two scale: w [nb][per_band] -> w16, w_scale [nb].
+hipError_t pack_f16(int nb, int64_t per_band, const float* w, void* w16, float* w_scale, hipStream_t s);
 // Number of states (binned = false) or bin-averaged DOS (binned = true) into out[ne][norb].
 hipError_t nos(const tetra_desc& d, const float* eps, const void* w, int wtype, const float* w_scale, float* out,
                bool binned, int shape, hipStream_t s);

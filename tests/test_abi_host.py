@@ -15,7 +15,7 @@ HEADER = os.path.join(ROOT, "include", "tetra.h")
 def _declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(tetra_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(tetra_[a-z0-9_]+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
@@ -29,8 +29,9 @@ def L():
 
 def test_header_declares_the_entry_points():
     names = _declared_functions()
-    for n in ("tetra_dos_forward", "tetra_dos_backward", "tetra_dos_backward_ws", "tetra_dos_backward_workspace",
-              "tetra_dos_batched", "tetra_dos_batched_workspace",
+    for n in ("tetra_dos_forward", "tetra_dos_forward_ws", "tetra_dos_forward_workspace", "tetra_dos_backward",
+              "tetra_dos_backward_ws", "tetra_dos_backward_workspace", "tetra_dos_batched",
+              "tetra_dos_batched_workspace", "tetra_pack_f16",
               "tetra_nos_forward", "tetra_dos_binned", "tetra_status_string", "tetra_last_hip_error",
               "tetra_version"):
         assert n in names
@@ -39,6 +40,12 @@ def test_header_declares_the_entry_points():
 def test_every_declared_symbol_is_exported(L):
     for name in _declared_functions():
         assert hasattr(L, name), name
+
+
+def test_measurement_probe_is_not_in_the_product_library(L):
+    """The LDS-atomic probe is a benchmark helper of its own library, not part of the C ABI."""
+    assert "tetra_probe" not in open(HEADER).read()
+    assert not hasattr(L, "tetra_probe_lds_atomics")
 
 
 def test_status_strings(L):
@@ -94,8 +101,43 @@ def test_forward_rejects_bad_pointers_and_flags(L):
     assert _fwd(L, d) == -1
     assert _fwd(L, good(), flags=7 << 8) == -1  # no such tile shape
     assert _fwd(L, good(), flags=15 << 8) == -1
-    assert _fwd(L, good(), flags=1 | (2 << 8)) == -2  # exact mode only with the default tile
-    assert _fwd(L, good(), flags=2 | (3 << 8)) == -2  # deterministic (= exact) mode likewise
+    assert _fwd(L, good(), flags=1) == -3  # exact mode needs a workspace
+    assert _fwd(L, good(), flags=2 | (3 << 8)) == -3  # deterministic (= exact) mode likewise
+
+
+def _fwd_ws(L, d, ws, ws_bytes, flags=0):
+    return L.tetra_dos_forward_ws(ctypes.byref(d), FAKE, FAKE, 0, None, FAKE, flags, ws, ws_bytes, None)
+
+
+def test_forward_workspace_sizes_and_checks(L):
+    d = good()
+    need = 256 + 8 * d.ne * d.norb
+    for flags in (1, 2, 3, 1 | (5 << 8)):
+        assert L.tetra_dos_forward_workspace(ctypes.byref(d), flags) == need
+    assert L.tetra_dos_forward_workspace(ctypes.byref(d), 0) == 0
+    assert L.tetra_dos_forward_workspace(ctypes.byref(d), 3 << 8) == 0
+    assert L.tetra_dos_forward_workspace(ctypes.byref(d), 0x10) == 0  # unknown flag
+    assert L.tetra_dos_forward_workspace(ctypes.byref(d), 1 | (6 << 8)) == 0  # no such tile shape
+    bad = good()
+    bad.de = -1.0
+    assert L.tetra_dos_forward_workspace(ctypes.byref(bad), 1) == 0
+    assert tetra.forward_workspace_bytes((4, 4, 4), 2, 3, -1.0, 0.01, 100, exact=True) == need
+    assert _fwd_ws(L, d, FAKE, need - 1, flags=1) == -3  # too small
+    assert _fwd_ws(L, d, None, need, flags=1) == -3  # missing
+    assert _fwd_ws(L, d, FAKE + 8, need, flags=1) == -1  # misaligned
+    assert _fwd_ws(L, bad, FAKE, need, flags=1) == -1
+    assert _fwd_ws(L, d, FAKE, need, flags=0x40) == -1  # unknown flag
+
+
+def test_pack_f16_rejects_bad_arguments(L):
+    f = L.tetra_pack_f16
+    assert f(0, 2, 3, FAKE, FAKE, FAKE, None) == -1
+    assert f(2, 0, 3, FAKE, FAKE, FAKE, None) == -1
+    assert f(2, 2, -1, FAKE, FAKE, FAKE, None) == -1
+    assert f(2, 2, 3, None, FAKE, FAKE, None) == -1
+    assert f(2, 2, 3, FAKE, None, FAKE, None) == -1
+    assert f(2, 2, 3, FAKE, FAKE, None, None) == -1
+    assert f(1 << 16, 1 << 8, 1 << 7, FAKE, FAKE, FAKE, None) == -1  # 2^31 elements
 
 
 def test_backward_rejects_bad_arguments(L):
@@ -177,11 +219,14 @@ def test_from_eigh_layouts():
     assert torch.allclose(a[1, 2, 4].to(torch.complex128), vec[4, 2, 1], atol=1e-6)
 
 
-def test_probe_rejects_bad_arguments(L):
-    assert L.tetra_probe_lds_atomics(0, 10, FAKE, None) == -1
-    assert L.tetra_probe_lds_atomics(4, 0, FAKE, None) == -1
-    assert L.tetra_probe_lds_atomics(4, 10, None, None) == -1
-    assert L.tetra_probe_lds_atomics((1 << 24) + 1, 10, FAKE, None) == -1
+def test_probe_rejects_bad_arguments():
+    from paper_1710_10789_amd import probe
+
+    P = probe.lib()
+    assert P.tetra_probe_lds_atomics(0, 10, FAKE, None) == -1
+    assert P.tetra_probe_lds_atomics(4, 0, FAKE, None) == -1
+    assert P.tetra_probe_lds_atomics(4, 10, None, None) == -1
+    assert P.tetra_probe_lds_atomics((1 << 24) + 1, 10, FAKE, None) == -1
 
 
 def test_backward_workspace_sizes(L):

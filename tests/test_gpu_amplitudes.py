@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 import synth
-from test_gpu_backward import gate
+from gates import gate
 
 pytestmark = pytest.mark.gpu
 
@@ -53,7 +53,7 @@ def test_forward_kernels_square_the_amplitudes(torch_dev, oracle_lib, model):
     te, ta = torch.from_numpy(eps).to(dev), torch.from_numpy(a).to(dev)
     print(f"[case] amplitudes {GRID} norb={NORB} ne={NE}: DOS, number of states, bin averages", flush=True)
     d = tetra.dos_forward(te, ta, GRID, e0, de, NE)
-    dk = tetra.dos_forward(te, ta, GRID, e0, de, NE, kahan=True)
+    dk = tetra.dos_forward(te, ta, GRID, e0, de, NE, exact=True)
     n = tetra.nos_forward(te, ta, GRID, e0, de, NE)
     nb_ = tetra.dos_binned(te, ta, GRID, e0, de, NE)
     torch.cuda.synchronize()

@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 import synth
-from test_gpu_backward import gate
+from gates import gate
 
 pytestmark = pytest.mark.gpu
 
@@ -147,7 +147,7 @@ def test_two_phase_fp16_and_amplitudes(torch_dev, oracle_lib):
     ra = 2.0 * a.astype(np.complex128) * rb
     assert gate(ge.cpu().numpy(), re)[0] and gate(ga.real, ra.real)[0] and gate(ga.imag, ra.imag)[0]
     # FP16 weights: the gradient is that of the dequantised weights
-    w16, scale = tetra.half_weights(torch.from_numpy(b))
+    w16, scale = (t.cpu() for t in tetra.half_weights(torch.from_numpy(b).cuda()))
     wd = (w16.float() * scale[:, None, None]).numpy()
     re, rw = oracle_lib.dos_backward(eps, wd, grid, e0, de, G.astype(np.float64))
     print("[case] two-phase FP16 weights, tile 2", flush=True)

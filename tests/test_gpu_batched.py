@@ -80,7 +80,7 @@ def test_batched_fp16_weights(torch_dev, oracle_lib):
     for seed, grid, ne in ((1, (6, 7, 20), 300), (2, (12, 4, 9), 700)):
         eps, w = synth.band_structure(8, seed, grid)
         e0, de = synth.energy_grid(eps, ne)
-        w16, scale = tetra.half_weights(torch.from_numpy(w))
+        w16, scale = (t.cpu() for t in tetra.half_weights(torch.from_numpy(w).cuda()))
         deq = (w16.float() * scale[:, None, None]).numpy()
         probs.append((torch.from_numpy(eps).to(dev), w16.to(dev), grid, e0, de, ne, scale.to(dev)))
         refs.append(oracle_lib.dos(eps, deq, grid, e0, de, ne)[0])
@@ -152,7 +152,7 @@ def test_batched_sixteen_orbitals_fp16(torch_dev, oracle_lib):
     for seed, grid, ne in ((21, (8, 9, 10), 700), (22, (12, 5, 16), 1300), (23, (3, 4, 33), 256)):
         eps, w = synth.band_structure(16, seed, grid)
         e0, de = synth.energy_grid(eps, ne)
-        w16, scale = tetra.half_weights(torch.from_numpy(w))
+        w16, scale = (t.cpu() for t in tetra.half_weights(torch.from_numpy(w).cuda()))
         deq = (w16.float() * scale[:, None, None]).numpy()
         probs.append((torch.from_numpy(eps).to(dev), w16.to(dev), grid, e0, de, ne, scale.to(dev)))
         refs.append(oracle_lib.dos(eps, deq, grid, e0, de, ne)[0])

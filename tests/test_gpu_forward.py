@@ -152,7 +152,7 @@ def _fp16_inputs(w):
 
     import paper_1710_10789_amd as tetra
 
-    w16, scale = tetra.half_weights(torch.from_numpy(w))
+    w16, scale = (t.cpu() for t in tetra.half_weights(torch.from_numpy(w).cuda()))
     deq = (w16.float() * scale[:, None, None]).numpy()
     return w16, scale, deq
 
@@ -177,18 +177,60 @@ def test_fp16_weights(torch_dev, oracle_lib):
 
 @pytest.mark.parametrize("grid,norb,ne", [((16, 16, 16), 8, 200), ((5, 7, 3), 3, 150), ((9, 6, 21), 16, 3000)])
 def test_exact_accumulation_mode(torch_dev, oracle_lib, grid, norb, ne):
-    """TETRA_KAHAN: exact cross-workgroup sums; parity with the oracle and bitwise reproducibility."""
+    """TETRA_EXACT: exact cross-workgroup sums; parity with the oracle and bitwise reproducibility."""
     torch, dev = torch_dev
     import paper_1710_10789_amd as tetra
 
     eps, w = synth.band_structure(norb, 2, grid)
     e0, de = synth.energy_grid(eps, ne)
     te, tw = torch.from_numpy(eps).to(dev), torch.from_numpy(w).to(dev)
-    a = tetra.dos_forward(te, tw, grid, e0, de, ne, kahan=True)
-    b = tetra.dos_forward(te, tw, grid, e0, de, ne, kahan=True)
+    a = tetra.dos_forward(te, tw, grid, e0, de, ne, exact=True)
+    b = tetra.dos_forward(te, tw, grid, e0, de, ne, exact=True)
     torch.cuda.synchronize()
     ref, _ = oracle_lib.dos(eps, w, grid, e0, de, ne)
     err = _err(a.cpu().numpy().astype(np.float64), ref)
     print(f"[case] exact-mode err {err:.3e}", flush=True)
     assert err <= TOL_F32
     assert torch.equal(a, b)
+
+
+def test_exact_mode_every_tile_shape_and_graph_replays(torch_dev, oracle_lib):
+    """TETRA_EXACT on every tile shape: oracle parity and bitwise repeats; the exact forward (set-up,
+    bound pass, main pass, conversion, all plain kernels into the caller's workspace) captured in a
+    HIP graph and replayed several times with eager work in between, every replay bitwise equal to
+    the eager call."""
+    torch, dev = torch_dev
+    import paper_1710_10789_amd as tetra
+
+    grid, norb, ne = (16, 16, 32), 8, 300
+    eps, w = synth.band_structure(norb, 6, grid)
+    e0, de = synth.energy_grid(eps, ne)
+    ref, _ = oracle_lib.dos(eps, w, grid, e0, de, ne)
+    te, tw = torch.from_numpy(eps).to(dev), torch.from_numpy(w).to(dev)
+    for tile in range(len(tetra.TILE_SHAPES)):
+        print(f"[case] exact mode, tile {tile}", flush=True)
+        a = tetra.dos_forward(te, tw, grid, e0, de, ne, exact=True, tile=tile)
+        b = tetra.dos_forward(te, tw, grid, e0, de, ne, deterministic=True, tile=tile)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+        assert _err(a.cpu().numpy().astype(np.float64), ref) <= TOL_F32
+    nbytes = tetra.forward_workspace_bytes(grid, norb, norb, e0, de, ne, exact=True)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    out = torch.empty((ne, norb), device=dev)
+    eager = tetra.dos_forward(te, tw, grid, e0, de, ne, exact=True, workspace=ws).clone()
+    print("[case] exact mode in a HIP graph", flush=True)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            tetra.dos_forward(te, tw, grid, e0, de, ne, exact=True, workspace=ws, out=out)
+    torch.cuda.current_stream().wait_stream(s)
+    for r in range(3):
+        out.fill_(float("nan"))
+        ws.fill_(0xA5)  # stale workspace contents must not matter
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), r
+        tetra.dos_forward(te, tw * 0.5, grid, e0, de, ne)  # eager work in between
+        torch.cuda.synchronize()

@@ -102,7 +102,7 @@ def test_fp16_weights(torch_dev, oracle_lib):
     grid, norb, ne = (12, 10, 9), 7, 90
     eps, w = synth.band_structure(norb, 9, grid)
     e0, de = _grid_inside(eps, ne, 0.1, 0.9)
-    w16, scale = tetra.half_weights(torch.from_numpy(w))
+    w16, scale = (t.cpu() for t in tetra.half_weights(torch.from_numpy(w).cuda()))
     deq = (w16.float() * scale[:, None, None]).numpy()
     rn = oracle_lib.nos(eps, deq, grid, e0, de, ne)
     rb = oracle_lib.dos_binned(eps, deq, grid, e0, de, ne)

@@ -42,17 +42,17 @@ def test_fp16_weights_exact_accumulation(torch_dev, oracle_lib, model):
     import paper_1710_10789_amd as tetra
 
     eps, w, e0, de, ref32 = model
-    w16, scale = tetra.half_weights(torch.from_numpy(w))
+    w16, scale = (t.cpu() for t in tetra.half_weights(torch.from_numpy(w).cuda()))
     deq = (w16.float() * scale[:, None, None]).numpy()
     refdq, _ = oracle_lib.dos(eps, deq, GRID, e0, de, NE)
     te, w16d, sd = torch.from_numpy(eps).to(dev), w16.to(dev), scale.to(dev)
     print(f"[case] {GRID} nb=norb={NORB} ne={NE} fp16 + exact", flush=True)
-    for kahan in (False, True):
-        got = tetra.dos_forward(te, w16d, GRID, e0, de, NE, w_scale=sd, kahan=kahan)
+    for exact in (False, True):
+        got = tetra.dos_forward(te, w16d, GRID, e0, de, NE, w_scale=sd, exact=exact)
         torch.cuda.synchronize()
         got = got.cpu().numpy().astype(np.float64)
         e32, edq = _err(got, ref32), _err(got, refdq)
-        print(f"[case] kahan={kahan}: err vs fp32 weights {e32:.3e}, vs dequantised {edq:.3e}", flush=True)
+        print(f"[case] exact={exact}: err vs fp32 weights {e32:.3e}, vs dequantised {edq:.3e}", flush=True)
         assert e32 <= 1e-3 and edq <= 1e-5
 
 
@@ -62,7 +62,7 @@ def test_exact_fp32_and_repeat_spread(torch_dev, model):
 
     eps, w, e0, de, ref = model
     te, tw = torch.from_numpy(eps).to(dev), torch.from_numpy(w).to(dev)
-    exact = [tetra.dos_forward(te, tw, GRID, e0, de, NE, kahan=True) for _ in range(3)]
+    exact = [tetra.dos_forward(te, tw, GRID, e0, de, NE, exact=True) for _ in range(3)]
     plain = [tetra.dos_forward(te, tw, GRID, e0, de, NE) for _ in range(3)]
     torch.cuda.synchronize()
     assert all(torch.equal(exact[0], x) for x in exact[1:])

@@ -3,6 +3,7 @@ import numpy as np
 import pytest
 
 import synth
+from gates import gate
 
 pytestmark = pytest.mark.gpu
 
@@ -37,8 +38,10 @@ def test_every_tile_shape_forward_and_backward(torch_dev, oracle_lib, tile, grid
     ref, _ = oracle_lib.dos(eps, w, grid, e0, de, 170)
     assert _err(got.cpu().numpy().astype(np.float64), ref) <= 1e-5
     re, rw = oracle_lib.dos_backward(eps, w, grid, e0, de, G.astype(np.float64))
-    assert _err(ge.cpu().numpy().astype(np.float64), re) <= 1e-5
-    assert _err(gw.cpu().numpy().astype(np.float64), rw) <= 1e-5
+    oke, eb, en = gate(ge.cpu().numpy(), re)
+    okw, wb, wn = gate(gw.cpu().numpy(), rw)
+    print(f"[case] grad_eps worst-rel {eb:.2e} norm {en:.2e}; grad_w worst-rel {wb:.2e} norm {wn:.2e}", flush=True)
+    assert oke and okw
 
 
 def test_autotuner_picks_a_shape_and_caches_it(torch_dev, tmp_path, monkeypatch):

@@ -99,3 +99,19 @@ def test_gradient_of_separable_band_closed_form(oracle_lib):
                 ref[(i + 1) % n1] -= G[j, 0] * s
     got = ge[0].reshape(n1, n2 * n3).sum(axis=1)
     np.testing.assert_allclose(got, ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("grid", [(1, 3, 4), (2, 3, 3), (3, 2, 5), (5, 4, 3), (6, 3, 2)])
+def test_oracle_results_do_not_depend_on_the_thread_count(oracle_lib, grid):
+    """The forward's slabs and the backward's (band, slab) phases sum every element in a fixed order,
+    so one thread and eight give the same bits (odd and even slab counts, a single slab)."""
+    eps, w = synth.band_structure(3, 21, grid)
+    e0, de = synth.energy_grid(eps, 60)
+    G = np.random.default_rng(3).normal(size=(60, 3))
+    d1, c1 = oracle_lib.dos(eps, w, grid, e0, de, 60, nthreads=1)
+    d8, c8 = oracle_lib.dos(eps, w, grid, e0, de, 60, nthreads=8)
+    assert c1 == c8 and np.array_equal(d1, d8)
+    e1, w1 = oracle_lib.dos_backward(eps, w, grid, e0, de, G, nthreads=1)
+    e8, w8 = oracle_lib.dos_backward(eps, w, grid, e0, de, G, nthreads=8)
+    assert np.array_equal(e1, e8) and np.array_equal(w1, w8)
+    assert np.abs(e1).max() > 0 and np.abs(w1).max() > 0
