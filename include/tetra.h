@@ -52,7 +52,8 @@ typedef enum {
   TETRA_ERR_ARG = -1,         /* null pointer, bad size, bad grid, bad flag */
   TETRA_ERR_UNSUPPORTED = -2, /* valid request the library does not implement (e.g. norb > 16) */
   TETRA_ERR_WORKSPACE = -3,   /* workspace missing or too small */
-  TETRA_ERR_HIP = -4          /* a HIP runtime call or kernel launch failed */
+  TETRA_ERR_HIP = -4,         /* a HIP runtime call or kernel launch failed */
+  TETRA_ERR_SCRATCH = -5      /* problem too large for the static scratch of tetra_dos_forward_noalloc */
 } tetra_status;
 
 /* Storage type of the orbital weights w. */
@@ -134,6 +135,31 @@ size_t tetra_dos_forward_workspace(const tetra_desc* d, unsigned flags);
 tetra_status tetra_dos_forward_ws(const tetra_desc* d, const float* eps, const void* w, int wtype,
                                   const float* w_scale, float* dos, unsigned flags, void* workspace,
                                   size_t ws_bytes, void* stream);
+
+/*
+ * Largest ne*norb of an exact or deterministic call of tetra_dos_forward_noalloc: its static scratch
+ * holds 256 + 8*TETRA_NOALLOC_MAX_BINS bytes (2 MiB + 256) per device.
+ */
+#define TETRA_NOALLOC_MAX_BINS 262144
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): tetra_dos_forward_ws with the exact path's workspace taken from a
+ * static device array of the library instead of the caller. Same arguments, flags and result as
+ * tetra_dos_forward_ws (the caller still passes eps, w, w_scale and dos). With TETRA_EXACT or
+ * TETRA_DETERMINISTIC, ne*norb above TETRA_NOALLOC_MAX_BINS gives TETRA_ERR_SCRATCH before any HIP
+ * call; without them nothing of the scratch is used (the plain forward).
+ *
+ * The scratch is file-scope device memory that each device holds from the library's first call on
+ * it until the process ends; its device address is looked up once per device on that first call
+ * (hipGetSymbolAddress), so make the first call on a device outside graph capture. Every call on a
+ * device shares that device's one scratch: each call clears what must start at zero (with a kernel,
+ * no memset) and the scratch keeps the last call's contents afterwards, so exact calls that overlap
+ * on one device (concurrent streams, host threads, or graph replays in flight together) race and give
+ * wrong results; serialise them. Calls no hipMalloc, hipFree or allocating routine.
+ */
+tetra_status tetra_dos_forward_noalloc(const tetra_desc* d, const float* eps, const void* w, int wtype,
+                                       const float* w_scale, float* dos, unsigned flags, void* stream);
 
 /*
  * Adjoint of tetra_dos_forward for a scalar loss L with G = dL/dDOS (not in the paper; the

@@ -25,6 +25,8 @@ __all__ = [
     "make_desc",
     "dos_forward",
     "forward_workspace_bytes",
+    "dos_forward_noalloc",
+    "NOALLOC_MAX_BINS",
     "dos_backward",
     "backward_workspace_bytes",
     "nos_forward",
@@ -45,7 +47,9 @@ TETRA_W_F16 = 1
 TETRA_W_C32 = 2
 TETRA_EXACT = 1
 TETRA_DETERMINISTIC = 2
+TETRA_ERR_SCRATCH = -5
 MAX_NORB = 16
+NOALLOC_MAX_BINS = 262144  # ne*norb limit of the exact path of dos_forward_noalloc (TETRA_NOALLOC_MAX_BINS)
 # tile shapes (cubes along grid axes 1, 2, 3) selectable through the flags' bits 8..11
 TILE_SHAPES = ((4, 4, 16), (8, 8, 4), (4, 8, 8), (8, 4, 8), (4, 16, 4), (16, 4, 4))
 
@@ -113,6 +117,8 @@ def lib():
         L.tetra_dos_forward_workspace.restype = ctypes.c_size_t
         L.tetra_dos_forward_ws.argtypes = [ctypes.POINTER(TetraDesc), p, p, i, p, p, u, p, ctypes.c_size_t, p]
         L.tetra_dos_forward_ws.restype = i
+        L.tetra_dos_forward_noalloc.argtypes = [ctypes.POINTER(TetraDesc), p, p, i, p, p, u, p]
+        L.tetra_dos_forward_noalloc.restype = i
         L.tetra_pack_f16.argtypes = [i, i, i, p, p, p, p]
         L.tetra_pack_f16.restype = i
         L.tetra_nos_forward.argtypes = [ctypes.POINTER(TetraDesc), p, p, i, p, p, u, p]
@@ -293,6 +299,28 @@ def dos_forward(eps, w, grid, e0, de, ne, *, w_scale=None, exact=False, determin
         w_scale.data_ptr() if w_scale is not None else None, out.data_ptr(), flags, ws_ptr, ws_bytes,
         _stream_handle(dev))
     _check("tetra_dos_forward_ws", st)
+    return out
+
+
+def dos_forward_noalloc(eps, w, grid, e0, de, ne, out, *, w_scale=None, exact=False, deterministic=False,
+                        tile=None):
+    """``dos_forward`` through ``tetra_dos_forward_noalloc``: the exact path's workspace is the
+    library's static device scratch, so nothing is allocated (``out`` is required). Exact calls that
+    overlap on one device race on that scratch; ne*norb above ``NOALLOC_MAX_BINS`` raises
+    (``TETRA_ERR_SCRATCH``) with ``exact`` or ``deterministic``."""
+    torch = _torch()
+    nk, nb, norb = _shapes(eps, w, grid)
+    dev = eps.device
+    _require(eps, "eps", (nb, nk), (torch.float32,), dev)
+    _require(w, "w", (nb, norb, nk), _weight_dtypes(torch), dev)
+    wtype = _weights_type(torch, w, w_scale, nb, dev)
+    _require(out, "out", (int(ne), norb), (torch.float32,), dev)
+    d = make_desc(grid, nb, norb, e0, de, ne)
+    flags = (TETRA_EXACT if exact else 0) | (TETRA_DETERMINISTIC if deterministic else 0) | _tile_flag(tile)
+    st = lib().tetra_dos_forward_noalloc(
+        ctypes.byref(d), eps.data_ptr(), w.data_ptr(), wtype,
+        w_scale.data_ptr() if w_scale is not None else None, out.data_ptr(), flags, _stream_handle(dev))
+    _check("tetra_dos_forward_noalloc", st)
     return out
 
 

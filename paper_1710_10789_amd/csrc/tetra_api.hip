@@ -1,5 +1,6 @@
 // C ABI entry points (include/tetra.h): argument validation on the host, then kernel launches.
 
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -73,6 +74,63 @@ tetra_status tetra_dos_forward_ws(const tetra_desc* d, const float* eps, const v
 tetra_status tetra_dos_forward(const tetra_desc* d, const float* eps, const void* w, int wtype,
                                const float* w_scale, float* dos, unsigned flags, void* stream) {
   return tetra_dos_forward_ws(d, eps, w, wtype, w_scale, dos, flags, nullptr, 0, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Device memory of the allocation-free forward (tetra_dos_forward_noalloc): the exact path's bound
+// exponent and fixed-point sums live in this file-scope array instead of a caller's workspace. Each
+// device holds its own copy for the life of the process. In host code `scratch` is only a host-side
+// stand-in for the symbol: its device address comes from hipGetSymbolAddress, once per device with
+// that device current, and only that address is handed to kernels.
+constexpr size_t kStaticScratchBytes = 256 + 8 * (size_t)TETRA_NOALLOC_MAX_BINS;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kScratchDevices = 64;
+std::atomic<void*> g_scratch_ptr[kScratchDevices];
+
+// Device address of `scratch` on the current device (looked up on the first call per device;
+// concurrent first calls store the same address).
+hipError_t static_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kScratchDevices) return hipErrorInvalidDevice;
+  void* p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+  if (!p) {
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev].store(p, std::memory_order_release);
+  }
+  *out = p;
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+tetra_status tetra_dos_forward_noalloc(const tetra_desc* d, const float* eps, const void* w, int wtype,
+                                       const float* w_scale, float* dos, unsigned flags, void* stream) {
+  tetra_status st = check_desc(d);
+  if (st != TETRA_OK) return st;
+  if (!eps || !w || !dos) return TETRA_ERR_ARG;
+  if ((st = check_weights(wtype, w_scale)) != TETRA_OK) return st;
+  if (flags & ~(unsigned)(TETRA_EXACT | TETRA_DETERMINISTIC | TETRA_TILE_MASK)) return TETRA_ERR_ARG;
+  const int shape = (int)((flags & TETRA_TILE_MASK) >> 8);
+  if (shape >= tetra::kTileShapes) return TETRA_ERR_ARG;
+  const bool exact = (flags & (TETRA_EXACT | TETRA_DETERMINISTIC)) != 0;
+  if (exact && tetra::forward_exact_scratch_bytes(*d) > kStaticScratchBytes) return TETRA_ERR_SCRATCH;
+  void* ws = nullptr;
+  if (exact) {
+    const hipError_t e = static_scratch(&ws);
+    if (e != hipSuccess) return hip_status(e);
+  }
+  return hip_status(
+      tetra::forward(*d, eps, w, wtype, scale_of(wtype, w_scale), dos, ws, shape, (hipStream_t)stream));
 }
 
 tetra_status tetra_pack_f16(int nb, int norb, int nk, const float* w, void* w16, float* w_scale, void* stream) {
@@ -176,6 +234,7 @@ const char* tetra_status_string(int status) {
     case TETRA_ERR_UNSUPPORTED: return "unsupported request";
     case TETRA_ERR_WORKSPACE: return "workspace missing or too small";
     case TETRA_ERR_HIP: return "HIP runtime error";
+    case TETRA_ERR_SCRATCH: return "problem exceeds the static scratch of the allocation-free entry point";
     default: return "unknown status";
   }
 }

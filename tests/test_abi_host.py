@@ -54,6 +54,7 @@ def test_status_strings(L):
     assert L.tetra_status_string(-2) == b"unsupported request"
     assert L.tetra_status_string(-3) == b"workspace missing or too small"
     assert L.tetra_status_string(-4) == b"HIP runtime error"
+    assert b"static scratch" in L.tetra_status_string(-5)
     assert L.tetra_status_string(123) == b"unknown status"
     assert L.tetra_version() >= 100
 
@@ -127,6 +128,31 @@ def test_forward_workspace_sizes_and_checks(L):
     assert _fwd_ws(L, d, FAKE + 8, need, flags=1) == -1  # misaligned
     assert _fwd_ws(L, bad, FAKE, need, flags=1) == -1
     assert _fwd_ws(L, d, FAKE, need, flags=0x40) == -1  # unknown flag
+
+
+def _fwd_na(L, d, flags=0, eps=FAKE, dos=FAKE):
+    return L.tetra_dos_forward_noalloc(ctypes.byref(d) if d is not None else None, eps, FAKE, 0, None, dos, flags,
+                                       None)
+
+
+def test_noalloc_forward_rejects_before_any_hip_call(L):
+    """The allocation-free forward validates like tetra_dos_forward_ws and refuses exact problems
+    beyond its static scratch (TETRA_NOALLOC_MAX_BINS) with TETRA_ERR_SCRATCH, all without a GPU."""
+    text = open(HEADER).read()
+    assert f"#define TETRA_NOALLOC_MAX_BINS {tetra.NOALLOC_MAX_BINS}" in text
+    d = good()
+    assert _fwd_na(L, None) == -1
+    assert _fwd_na(L, d, eps=None) == -1
+    assert _fwd_na(L, d, dos=None) == -1
+    assert _fwd_na(L, d, flags=0x40) == -1  # unknown flag
+    assert _fwd_na(L, d, flags=1 | (6 << 8)) == -1  # no such tile shape
+    big = good()
+    big.norb, big.ne = 16, tetra.NOALLOC_MAX_BINS // 16 + 1
+    for flags in (1, 2, 3, 1 | (2 << 8)):
+        assert _fwd_na(L, big, flags=flags) == -5
+    bad = good()
+    bad.de = 0.0
+    assert _fwd_na(L, bad, flags=1) == -1
 
 
 def test_pack_f16_rejects_bad_arguments(L):
