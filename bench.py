@@ -281,9 +281,10 @@ def _time_events(torch, fn, steps, warmup):
     return ev[0].elapsed_time(ev[1]) / steps
 
 
-def bench_precision(args, torch, tetra, dev):
-    """128^3 grid, 16 bands x 16 orbitals, 2000 energies: FP16 weights with a per-band scale and the
-    exact accumulation, against plain FP32; errors against the FP64 oracle."""
+def precision_measurement(args, torch, tetra, dev, with_oracle=True):
+    """128^3 grid, 16 bands x 16 orbitals, 2000 energies: plain FP32, FP16 weights with a per-band scale,
+    and the exact accumulation of each; with ``with_oracle``, errors against the FP64 oracle (FP16
+    against the oracle on both the FP32 and the dequantised weights). Returns a dict."""
     from paper_1710_10789_amd import tune
 
     c = synth.config("k128_b16_e2000")
@@ -301,11 +302,15 @@ def bench_precision(args, torch, tetra, dev):
     w16, scale = tetra.half_weights(w)
     out = torch.empty((ne, norb), device=dev)
     tile, _ = tune.tune_forward(eps, w16, grid, e0, de, ne, w_scale=scale, reps=2)
+    ws = torch.empty(tetra.forward_workspace_bytes(grid, nb, norb, e0, de, ne, exact=True), dtype=torch.uint8,
+                     device=dev)
     runs = {
         "fp32": lambda: tetra.dos_forward(eps, w, grid, e0, de, ne, out=out, tile=tile),
         "fp16": lambda: tetra.dos_forward(eps, w16, grid, e0, de, ne, w_scale=scale, out=out, tile=tile),
-        "fp16_exact": lambda: tetra.dos_forward(eps, w16, grid, e0, de, ne, w_scale=scale, out=out, exact=True),
-        "fp32_exact": lambda: tetra.dos_forward(eps, w, grid, e0, de, ne, out=out, exact=True),
+        "fp16_exact": lambda: tetra.dos_forward(eps, w16, grid, e0, de, ne, w_scale=scale, out=out, exact=True,
+                                                tile=tile, workspace=ws),
+        "fp32_exact": lambda: tetra.dos_forward(eps, w, grid, e0, de, ne, out=out, exact=True, tile=tile,
+                                                workspace=ws),
     }
     print("[precision] timing", file=sys.stderr, flush=True)
     ms = {k: _time_events(torch, f, args.steps, args.warmup) for k, f in runs.items()}
@@ -315,25 +320,18 @@ def bench_precision(args, torch, tetra, dev):
         torch.cuda.synchronize()
         results[k] = out.cpu().numpy().astype(np.float64)
     rec = {
-        "metric": "tetra-band-energy updates/s, precision variant (FP16 weights, exact accumulation)",
-        "value": dense / (ms["fp16_exact"] * 1e-3),
-        "unit": "updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms["fp16_exact"],
-        "higher_is_better": True,
-        "dtype": "f32 math, f16 weights",
-        "data": "synthetic (seeded random 16-orbital tight-binding model)",
-        "config": {"workload": "k128_b16_e2000: 128^3 periodic k-grid, 16 bands x 16 orbitals, 2000 energies",
-                   "dense_updates_per_pass": dense, "in_window_updates_per_pass": uwin,
-                   "tile": list(tetra.TILE_SHAPES[tile]), "host_eigh_s": t_gen},
+        "workload": "k128_b16_e2000: 128^3 periodic k-grid, 16 bands x 16 orbitals, 2000 energies",
+        "dense_updates_per_pass": dense,
+        "in_window_updates_per_pass": uwin,
+        "tile": list(tetra.TILE_SHAPES[tile]),
+        "host_eigh_s": t_gen,
         "ms": ms,
+        "exact_over_plain": {"fp32": ms["fp32_exact"] / ms["fp32"], "fp16": ms["fp16_exact"] / ms["fp16"]},
         "updates_per_s": {k: dense / (v * 1e-3) for k, v in ms.items()},
         "hbm_gbs_algorithmic": {"fp32": (4 * nk * nb * (1 + norb)) / (ms["fp32"] * 1e-3) / 1e9,
                                 "fp16": (4 * nk * nb + 2 * nk * nb * norb) / (ms["fp16"] * 1e-3) / 1e9},
     }
-    if not args.no_cpu_baseline:
+    if with_oracle:
         import oracle
 
         oracle.build()
@@ -342,11 +340,83 @@ def bench_precision(args, torch, tetra, dev):
         t0 = time.perf_counter()
         ref, _ = oracle.dos(eps_np, w_np, grid, e0, de, ne, nthreads=cores)
         t_or = time.perf_counter() - t0
-        scale_ref = np.abs(ref).max()
-        rec["error_vs_fp64_oracle"] = {k: float(np.abs(v - ref).max() / scale_ref) for k, v in results.items()}
+        deq = (w16.float() * scale[:, None, None]).cpu().numpy()
+        del w_np
+        ref_dq, _ = oracle.dos(eps_np, deq, grid, e0, de, ne, nthreads=cores)
+        del deq
+        err = {k: float(np.abs(v - ref).max() / np.abs(ref).max()) for k, v in results.items()}
+        for k in ("fp16", "fp16_exact"):
+            err[k + "_vs_dequantised"] = float(np.abs(results[k] - ref_dq).max() / np.abs(ref_dq).max())
+        rec["error_vs_fp64_oracle"] = err
         rec["cpu_baseline"] = {"value": dense / t_or, "unit": "updates/s", "cores": cores, "kind": "oracle",
                                "sample": f"the whole workload, one forward pass, FP64 ({t_or:.1f} s)"}
+    del eps, w, w16, scale, out, ws
+    torch.cuda.empty_cache()
+    return rec
+
+
+def bench_precision(args, torch, tetra, dev):
+    """The precision workload on its own JSON line (value: the FP16 + exact forward)."""
+    p = precision_measurement(args, torch, tetra, dev, with_oracle=not args.no_cpu_baseline)
+    ms = p["ms"]["fp16_exact"]
+    rec = {
+        "metric": "tetra-band-energy updates/s, precision variant (FP16 weights, exact accumulation)",
+        "value": p["dense_updates_per_pass"] / (ms * 1e-3),
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "dtype": "f32 math, f16 weights",
+        "data": "synthetic (seeded random 16-orbital tight-binding model)",
+        "config": {"workload": p["workload"], "dense_updates_per_pass": p["dense_updates_per_pass"],
+                   "in_window_updates_per_pass": p["in_window_updates_per_pass"], "tile": p["tile"],
+                   "host_eigh_s": p["host_eigh_s"]},
+    }
+    for k in ("ms", "exact_over_plain", "updates_per_s", "hbm_gbs_algorithmic", "error_vs_fp64_oracle",
+              "cpu_baseline"):
+        if k in p:
+            rec[k] = p[k]
     print(json.dumps(rec), flush=True)
+
+
+def worst_case_forward_ms(torch, tetra, eps_np, w_np, grid, e0, de, ne, tile, steps=7):
+    """The paper's worst case (Sec. IV.A, GPU setup excluded): host-to-device copies of the inputs from
+    pinned host memory, the forward, and the device-to-host copy of the DOS; per-call event times over
+    ``steps`` calls: the paper's statistic (mean of the five shortest of seven) and the median."""
+    dev = torch.device("cuda:0")
+    h_eps = torch.empty(eps_np.shape, dtype=torch.float32, pin_memory=True)
+    h_w = torch.empty(w_np.shape, dtype=torch.float32, pin_memory=True)
+    h_eps.numpy()[...] = eps_np
+    h_w.numpy()[...] = w_np
+    nb, norb = w_np.shape[0], w_np.shape[1]
+    h_dos = torch.empty((ne, norb), dtype=torch.float32, pin_memory=True)
+    d_eps = torch.empty(eps_np.shape, dtype=torch.float32, device=dev)
+    d_w = torch.empty(w_np.shape, dtype=torch.float32, device=dev)
+    d_dos = torch.empty((ne, norb), dtype=torch.float32, device=dev)
+
+    def call():
+        d_eps.copy_(h_eps, non_blocking=True)
+        d_w.copy_(h_w, non_blocking=True)
+        tetra.dos_forward(d_eps, d_w, grid, e0, de, ne, out=d_dos, tile=tile)
+        h_dos.copy_(d_dos, non_blocking=True)
+
+    call()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(steps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        call()
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    bytes_moved = 4 * (eps_np.size + w_np.size + ne * norb)
+    srt = np.sort(ts)
+    return {"mean_5_shortest_of_7": float(srt[:5].mean()), "median": float(np.median(ts)),
+            "pcie_bytes": bytes_moved,
+            "what": "H2D of eps and w from pinned host memory + forward + D2H of dos, per call"}
 
 
 def bench_paper_shape(args, torch, tetra, dev):
@@ -548,6 +618,8 @@ def main():
     ap.add_argument("--mode", choices=["fwdbwd", "fwd"], default="fwdbwd")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tiles", help="forward,backward tile shape ids (skips the autotuner)")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="headline run without the 128^3 x 16 x 16 x 2000 precision workload's extra keys")
     ap.add_argument("--workload", choices=["headline", "precision", "batched", "paper", "nos"], default="headline",
                     help="headline: 64^3 x 8 x 8 x 1000 fwd+bwd (the metric); precision: 128^3 x 16 x 16 x 2000 "
                          "with FP16 weights and exact accumulation; batched: 32 models, one persistent launch; "
@@ -727,6 +799,7 @@ def main():
         "lds_atomic_ceiling": lds_ceiling,
         "kernel_source_sha": {k: kernel_source_hash(k) for k in KERNEL_SOURCES},
         "autotune_ms": {"forward": times_f, "backward": times_b},
+        "fwd_worst_case_ms": worst_case_forward_ms(torch, tetra, eps_np, w_np, grid, e0, de, ne, tile_f),
     }
     if not args.no_cpu_baseline:
         def gpu_fn():
@@ -738,6 +811,14 @@ def main():
         # the paper's best-case speedup (Sec. IV.A): one-core CPU time over the GPU kernel time of
         # the same forward pass, inputs resident on the device
         out["cpu_baseline"]["single_core_fwd_speedup"] = out["cpu_baseline"]["single_core_fwd_s"] / t_fwd
+        out["cpu_baseline"]["single_core_fwd_speedup_worst_case"] = (
+            out["cpu_baseline"]["single_core_fwd_s"] / (out["fwd_worst_case_ms"]["mean_5_shortest_of_7"] * 1e-3))
+    if not args.no_precision:
+        # the precision workload (not part of the headline value): times and errors of its four variants
+        del eps, w, teps, tw, dos, ge, gw, ws_b, target, G
+        torch.cuda.empty_cache()
+        out["precision_k128_b16_e2000"] = precision_measurement(args, torch, tetra, dev,
+                                                                with_oracle=not args.no_cpu_baseline)
     print(json.dumps(out), flush=True)
 
 
