@@ -49,6 +49,10 @@ def _load():
         lib.tetra_oracle_nos.restype = i
         lib.tetra_oracle_dos_backward.argtypes = [i, i, i, i, i, d, d, i, p, p, p, p, p, i]
         lib.tetra_oracle_dos_backward.restype = i
+        lib.tetra_oracle_tet_chi.argtypes = [p, p, p, d, d, d]
+        lib.tetra_oracle_tet_chi.restype = d
+        lib.tetra_oracle_chi.argtypes = [i, i, i, i, i, i, i, i, d, d, d, i, p, p, p, i]
+        lib.tetra_oracle_chi.restype = ll
         _lib = lib
     return _lib
 
@@ -157,3 +161,25 @@ def dos_backward(eps, w, grid, e0, de, G, nthreads=None):
     if rc != 0:
         raise ValueError("oracle rejected arguments")
     return ge, gw
+
+
+def tet_chi(e, ep, W, ef, E, vol):
+    """One tetrahedron's susceptibility spectral weight at transfer energy E: corner energies ``e``
+    (band n at k) and ``ep`` (band n' at k + q), interpolated weight ``W``, Fermi energy ``ef``."""
+    e = np.ascontiguousarray(e, dtype=np.float64)
+    ep = np.ascontiguousarray(ep, dtype=np.float64)
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    return _load().tetra_oracle_tet_chi(_ptr(e), _ptr(ep), _ptr(W), float(ef), float(E), float(vol))
+
+
+def chi(eps, w, grid, q, ef, w0, dw, nw, nthreads=None):
+    """FP64 orbital-resolved susceptibility spectral weight ``S[nw, norb]`` at w_j = w0 + j*dw for the
+    transfer ``q`` (grid steps), Fermi energy ``ef``; and the number of sub-tetrahedra. Im chi_0 = -pi S."""
+    eps, w, n1, n2, n3, nb, norb = _grid_args(eps, w, grid)
+    out = np.zeros((nw, norb), dtype=np.float64)
+    q1, q2, q3 = (int(x) for x in q)
+    cnt = _load().tetra_oracle_chi(n1, n2, n3, nb, norb, q1, q2, q3, float(ef), float(w0), float(dw), int(nw),
+                                   _ptr(eps), _ptr(w), _ptr(out), _threads(nthreads))
+    if cnt < 0:
+        raise ValueError("oracle rejected arguments")
+    return out, int(cnt)

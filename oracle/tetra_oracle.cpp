@@ -26,6 +26,19 @@
 //  R7 point values on E_j = e0 + j*de, j = 0..ne-1; no spin factor.
 //  R8 a tetrahedron-band with a non-finite corner energy contributes nothing.
 //
+// Susceptibility (the paper's stated future work, Sec. I and Sec. V; it prints no formulas): the
+// orbital-resolved imaginary part of the bare (Lindhard) susceptibility at zero temperature for a
+// momentum transfer q on the k-grid, as a spectral weight
+//   S_m(q, w) = sum_cubes sum_{tetrahedra of Table I} sum_{n,n'} (1/V_G) integral over the tetrahedron of
+//               W_m [theta(E_F - eps) theta(eps' - E_F) - theta(eps - E_F) theta(E_F - eps')] delta(w - (eps' - eps))
+// with eps = eps_n(k), eps' = eps_n'(k + q) and W_m = b_mn(k) b_mn'(k + q), each the linear interpolant
+// of its corner values within the tetrahedron (the linear tetrahedron method, as for the DOS), and
+// the step functions applied exactly. Im chi_0(q, w) = -pi S(q, w) in the convention
+// chi_0 = (1/N) sum [f(eps) - f(eps')] / (w + eps - eps' + i0). Evaluated by clipping each
+// tetrahedron (in barycentric coordinates) by the two occupation half-spaces into sub-tetrahedra and
+// summing, on each, the corner weights dw/dE of Sec. II.C with the difference energy eps' - eps in the
+// role of the band energy and the sub-tetrahedron's share of V_T.
+//
 // Parity: pinned in the CPU test suite against closed forms and independent geometry (cross-section
 // integrals of barycentric coordinates), derivative and normalisation identities, symmetries,
 // degenerate limits, a separable-grid closed form, histogram convergence and finite differences.
@@ -452,6 +465,253 @@ int tetra_oracle_dos_backward(int n1, int n2, int n3, int nb, int norb, double e
     }
   }
   return 0;
+}
+
+}  // extern "C"
+
+namespace {
+
+// A tetrahedron given by the barycentric coordinates (with respect to one tetrahedron of the grid) of
+// its four vertices.
+struct BaryTet {
+  double v[4][4];
+};
+
+// Volume of a sub-tetrahedron as a fraction of the parent's: |det| of its edge vectors in the
+// coordinates (lambda_1, lambda_2, lambda_3), which map the parent onto the unit simplex.
+double bary_volume_fraction(const BaryTet& t) {
+  double a[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int c = 0; c < 3; ++c) a[i][c] = t.v[i + 1][c + 1] - t.v[0][c + 1];
+  const double det = a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) -
+                     a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
+                     a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
+  return std::fabs(det);
+}
+
+// The part of tetrahedron `in` where the linear function f (values fc at the parent's corners) is
+// <= 0, as at most three tetrahedra appended to out. One vertex inside: the corner tetrahedron cut off
+// by the plane f = 0; two or three inside: a triangular prism (end triangles parallel to the cut),
+// split into three tetrahedra.
+void clip_halfspace(const BaryTet& in, const double fc[4], std::vector<BaryTet>& out) {
+  double f[4];
+  for (int i = 0; i < 4; ++i) {
+    f[i] = 0.0;
+    for (int c = 0; c < 4; ++c) f[i] += in.v[i][c] * fc[c];
+  }
+  int ins[4], outs[4], ni = 0, no = 0;
+  for (int i = 0; i < 4; ++i) {
+    if (f[i] <= 0.0) ins[ni++] = i;
+    else outs[no++] = i;
+  }
+  if (ni == 0) return;
+  if (ni == 4) {
+    out.push_back(in);
+    return;
+  }
+  // point on the edge from inside vertex a to outside vertex b where f = 0
+  auto cut = [&](int a, int b, double p[4]) {
+    const double t = f[a] / (f[a] - f[b]);
+    for (int c = 0; c < 4; ++c) p[c] = in.v[a][c] + t * (in.v[b][c] - in.v[a][c]);
+  };
+  auto prism = [&](const double* p0, const double* p1, const double* p2, const double* q0, const double* q1,
+                   const double* q2) {
+    const double* tets[3][4] = {{p0, p1, p2, q2}, {p0, p1, q1, q2}, {p0, q0, q1, q2}};
+    for (int k = 0; k < 3; ++k) {
+      BaryTet t;
+      for (int i = 0; i < 4; ++i)
+        for (int c = 0; c < 4; ++c) t.v[i][c] = tets[k][i][c];
+      out.push_back(t);
+    }
+  };
+  if (ni == 1) {
+    BaryTet t;
+    const int a = ins[0];
+    for (int c = 0; c < 4; ++c) t.v[0][c] = in.v[a][c];
+    for (int k = 0; k < 3; ++k) cut(a, outs[k], t.v[k + 1]);
+    out.push_back(t);
+  } else if (ni == 2) {
+    const int a = ins[0], b = ins[1], c = outs[0], d = outs[1];
+    double ac[4], ad[4], bc[4], bd[4];
+    cut(a, c, ac);
+    cut(a, d, ad);
+    cut(b, c, bc);
+    cut(b, d, bd);
+    prism(in.v[a], ac, ad, in.v[b], bc, bd);
+  } else {
+    const int a = ins[0], b = ins[1], c = ins[2], d = outs[0];
+    double ad[4], bd[4], cd[4];
+    cut(a, d, ad);
+    cut(b, d, bd);
+    cut(c, d, cd);
+    prism(in.v[a], in.v[b], in.v[c], ad, bd, cd);
+  }
+}
+
+// Sub-tetrahedra of the region {f1 <= 0} and {f2 <= 0} of the parent tetrahedron.
+void clip_two(const double f1[4], const double f2[4], std::vector<BaryTet>& out) {
+  BaryTet whole;
+  for (int i = 0; i < 4; ++i)
+    for (int c = 0; c < 4; ++c) whole.v[i][c] = i == c ? 1.0 : 0.0;
+  std::vector<BaryTet> first;
+  clip_halfspace(whole, f1, first);
+  for (const BaryTet& t : first) clip_halfspace(t, f2, out);
+}
+
+// Spectral weight of one tetrahedron at transfer energy E (see the header): corner values eps, eps'
+// and W in any order, Fermi energy ef, vol = V_T/V_G.
+double tet_chi(const double e[4], const double ep[4], const double W[4], double ef, double E, double vol) {
+  double total = 0.0;
+  for (int region = 0; region < 2; ++region) {
+    // region 0: eps <= E_F <= eps' (sign +1); region 1: eps' <= E_F <= eps (sign -1)
+    double f1[4], f2[4];
+    for (int c = 0; c < 4; ++c) {
+      f1[c] = region == 0 ? e[c] - ef : ef - e[c];
+      f2[c] = region == 0 ? ef - ep[c] : ep[c] - ef;
+    }
+    std::vector<BaryTet> subs;
+    clip_two(f1, f2, subs);
+    for (const BaryTet& t : subs) {
+      const double frac = bary_volume_fraction(t);
+      if (!(frac > 0.0)) continue;
+      double d[4], w[4];
+      for (int i = 0; i < 4; ++i) {
+        d[i] = 0.0;
+        w[i] = 0.0;
+        for (int c = 0; c < 4; ++c) {
+          d[i] += t.v[i][c] * (ep[c] - e[c]);
+          w[i] += t.v[i][c] * W[c];
+        }
+      }
+      const double v = tetra_oracle_tet_dos(d, w, E, vol * frac);
+      total += region == 0 ? v : -v;
+    }
+  }
+  return total;
+}
+
+// Adds one tetrahedron-band-pair's spectral weight at every grid energy inside its sub-tetrahedra's
+// windows: acc[j][m] += S_m(w_j) for the corner weights Wc[c][m] (norb per corner). Returns the
+// number of sub-tetrahedra with positive volume.
+int chi_accumulate(const Grid& g, const double e[4], const double ep[4], const double* Wc, double ef, double vol,
+                   double* acc) {
+  const int norb = g.norb;
+  int nsub = 0;
+  for (int region = 0; region < 2; ++region) {
+    double f1[4], f2[4];
+    for (int c = 0; c < 4; ++c) {
+      f1[c] = region == 0 ? e[c] - ef : ef - e[c];
+      f2[c] = region == 0 ? ef - ep[c] : ep[c] - ef;
+    }
+    const double sign = region == 0 ? 1.0 : -1.0;
+    std::vector<BaryTet> subs;
+    clip_two(f1, f2, subs);
+    for (const BaryTet& t : subs) {
+      const double frac = bary_volume_fraction(t);
+      if (!(frac > 0.0)) continue;
+      ++nsub;
+      double d[4], ds[4];
+      int perm[4];
+      for (int i = 0; i < 4; ++i) {
+        d[i] = 0.0;
+        for (int c = 0; c < 4; ++c) d[i] += t.v[i][c] * (ep[c] - e[c]);
+      }
+      sort4(d, ds, perm);
+      for (int j = first_above(g, ds[0]); j < g.ne; ++j) {
+        const double E = g.energy(j);
+        if (E >= ds[3]) break;
+        double wl[4], gl[4];
+        corner_weights<double>(ds, E, vol * frac / 4.0, wl, gl);
+        for (int m = 0; m < norb; ++m) {
+          double s = 0.0;
+          for (int l = 0; l < 4; ++l) {
+            double wv = 0.0;  // W at sub-tetrahedron vertex perm[l]
+            for (int c = 0; c < 4; ++c) wv += t.v[perm[l]][c] * Wc[c * norb + m];
+            s += wv * gl[l];
+          }
+          acc[(size_t)j * norb + m] += sign * s;
+        }
+      }
+    }
+  }
+  return nsub;
+}
+
+}  // namespace
+
+extern "C" {
+
+// One tetrahedron's contribution to the susceptibility spectral weight S (see the header) at transfer
+// energy E: corner energies e (band n at k), ep (band n' at k + q), interpolated weight W, Fermi
+// energy ef; vol = V_T/V_G. Corners in any order.
+double tetra_oracle_tet_chi(const double e[4], const double ep[4], const double W[4], double ef, double E,
+                            double vol) {
+  for (int c = 0; c < 4; ++c)
+    if (!std::isfinite(e[c]) || !std::isfinite(ep[c])) return 0.0;
+  return tet_chi(e, ep, W, ef, E, vol);
+}
+
+// Orbital-resolved susceptibility spectral weight on the periodic grid for the transfer q = (q1, q2, q3)
+// in grid steps (any sign, periodic): out[j][m] = S_m(q, w0 + j*dw) (header), FP64, overwritten.
+//   eps [nb][nk] FP32, w [nb][norb][nk] FP32 (b = |a|^2), host memory.
+// Sums over every band pair (n, n'). A tetrahedron with a non-finite corner energy in either band
+// contributes nothing. Slabs of constant i1 with one partial each, reduced in slab order. Returns
+// the number of sub-tetrahedra with positive volume, or -1 on invalid arguments.
+long long tetra_oracle_chi(int n1, int n2, int n3, int nb, int norb, int q1, int q2, int q3, double ef,
+                           double w0, double dw, int nw, const float* eps, const float* w, double* out,
+                           int nthreads) {
+  const Grid g{n1, n2, n3, nb, norb, nw, w0, dw};
+  if (!grid_ok(g) || !eps || !w || !out || !std::isfinite(ef)) return -1;
+  const int64_t nk = g.nk();
+  const double vol = 1.0 / (6.0 * (double)nk);
+  const size_t nbins = (size_t)nw * norb;
+  const int s1 = ((q1 % n1) + n1) % n1, s2 = ((q2 % n2) + n2) % n2, s3 = ((q3 % n3) + n3) % n3;
+  std::vector<double> partial((size_t)n1 * nbins, 0.0);
+  std::vector<long long> counts(n1, 0);
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+  for (int i1 = 0; i1 < n1; ++i1) {
+    double* acc = &partial[(size_t)i1 * nbins];
+    long long nsub = 0;
+    std::vector<double> Wc(4 * (size_t)norb);
+    for (int i2 = 0; i2 < n2; ++i2)
+      for (int i3 = 0; i3 < n3; ++i3)
+        for (int t = 0; t < 6; ++t) {
+          int64_t kk[4], kq[4];
+          tet_kpoints(g, i1, i2, i3, t, kk);
+          for (int l = 0; l < 4; ++l) {
+            const int64_t a = kk[l] / ((int64_t)n2 * n3), b = (kk[l] / n3) % n2, c = kk[l] % n3;
+            kq[l] = (((a + s1) % n1) * n2 + (b + s2) % n2) * n3 + (c + s3) % n3;
+          }
+          for (int n = 0; n < nb; ++n)
+            for (int np = 0; np < nb; ++np) {
+              double e[4], ep[4];
+              bool finite = true;
+              for (int l = 0; l < 4; ++l) {
+                e[l] = (double)eps[(int64_t)n * nk + kk[l]];
+                ep[l] = (double)eps[(int64_t)np * nk + kq[l]];
+                finite = finite && std::isfinite(e[l]) && std::isfinite(ep[l]);
+              }
+              if (!finite) continue;
+              for (int l = 0; l < 4; ++l)
+                for (int m = 0; m < norb; ++m)
+                  Wc[(size_t)l * norb + m] = (double)w[((int64_t)n * norb + m) * nk + kk[l]] *
+                                             (double)w[((int64_t)np * norb + m) * nk + kq[l]];
+              nsub += chi_accumulate(g, e, ep, Wc.data(), ef, vol, acc);
+            }
+        }
+    counts[i1] = nsub;
+  }
+  long long total = 0;
+  std::fill(out, out + nbins, 0.0);
+  for (int i1 = 0; i1 < n1; ++i1) {
+    total += counts[i1];
+    const double* acc = &partial[(size_t)i1 * nbins];
+    for (size_t q = 0; q < nbins; ++q) out[q] += acc[q];
+  }
+  return total;
 }
 
 }  // extern "C"
