@@ -540,6 +540,67 @@ def bench_nos(args, torch, tetra, dev):
     print(json.dumps(rec), flush=True)
 
 
+def bench_chi(args, torch, tetra, dev):
+    """Susceptibility spectral weight at the headline model: 64^3 grid, 8 bands x 8 orbitals, transfer
+    q = (16, 16, 0) grid steps, 500 transfer energies from 0 to the band width, Fermi energy at half
+    filling; every band pair. One JSON line (not the headline metric)."""
+    c = synth.config("chi_k64_b8_w500")
+    grid, norb, nw, q = c["grid"], c["norb"], c["nw"], c["q"]
+    eps_np, w_np = synth.band_structure(norb, c["seed"], grid)
+    ef, w0, dw = synth.chi_grid(eps_np, nw)
+    nb, nk = eps_np.shape
+    dense = 6 * nk * nb * nb * nw
+    eps = torch.from_numpy(eps_np).to(dev)
+    w = torch.from_numpy(w_np).to(dev)
+    out = torch.empty((nw, norb), device=dev)
+    # tile shape: each of the six timed (best of three launches), outside the timed region
+    times = []
+    for tile in range(len(tetra.TILE_SHAPES)):
+        times.append(_time_events(torch, lambda: tetra.chi_spectral(eps, w, grid, q, ef, w0, dw, nw, out=out,
+                                                                     tile=tile), 3, 1))
+    tile = int(np.argmin(times))
+    ms = _time_events(torch, lambda: tetra.chi_spectral(eps, w, grid, q, ef, w0, dw, nw, out=out, tile=tile),
+                      args.steps, args.warmup)
+    got = out.cpu().numpy().astype(np.float64)
+    rec = {
+        "metric": "susceptibility spectral-weight (tetrahedron, band pair, transfer energy) updates/s at 64^3, "
+                  "8 bands x 8 orbitals, 500 w",
+        "value": dense / (ms * 1e-3),
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "dtype": "f32",
+        "data": "synthetic (seeded random 8-orbital tight-binding model; eigh on the host, untimed)",
+        "config": {"workload": "chi_k64_b8_w500: 64^3 periodic k-grid, 8 bands x 8 orbitals, q = (16, 16, 0), "
+                               "500 transfer energies, E_F at half filling",
+                   "dense_updates_per_pass": dense, "tile": list(tetra.TILE_SHAPES[tile])},
+        "tile_ms": times,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+
+        oracle.build()
+        cores = len(os.sched_getaffinity(0))
+        print(f"[chi] FP64 oracle on {cores} threads", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        ref, upd = oracle.chi(eps_np, w_np, grid, q, ef, w0, dw, nw, nthreads=cores)
+        t_or = time.perf_counter() - t0
+        flops = algorithmic_flops(upd, norb)[0]
+        achieved = flops / (ms * 1e-3) / 1e12
+        rec["config"]["in_window_updates_per_pass"] = upd
+        rec["roofline"] = {"bound": "alu", "kernel": "chi_kernel", "achieved": achieved,
+                           "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                           "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": None,
+                           "algorithmic_flops_per_launch": flops, "avg_launch_ms": ms}
+        rec["error_vs_fp64_oracle"] = float(np.abs(got - ref).max() / np.abs(ref).max())
+        rec["cpu_baseline"] = {"value": dense / t_or, "unit": "updates/s", "cores": cores, "kind": "oracle",
+                               "sample": f"the whole workload, one pass, FP64 ({t_or:.1f} s)"}
+    print(json.dumps(rec), flush=True)
+
+
 def bench_batched(args, torch, tetra, dev):
     """32 independently seeded 8-orbital models, cubic grids from {24,32,48,64,96}^3 and 256..2048
     energies, through one persistent launch captured in a HIP graph, tile shapes per problem from the
@@ -620,11 +681,12 @@ def main():
     ap.add_argument("--tiles", help="forward,backward tile shape ids (skips the autotuner)")
     ap.add_argument("--no-precision", action="store_true",
                     help="headline run without the 128^3 x 16 x 16 x 2000 precision workload's extra keys")
-    ap.add_argument("--workload", choices=["headline", "precision", "batched", "paper", "nos"], default="headline",
+    ap.add_argument("--workload", choices=["headline", "precision", "batched", "paper", "nos", "chi"], default="headline",
                     help="headline: 64^3 x 8 x 8 x 1000 fwd+bwd (the metric); precision: 128^3 x 16 x 16 x 2000 "
                          "with FP16 weights and exact accumulation; batched: 32 models, one persistent launch; "
                          "paper: the paper's 60 x 60 x 10 x 8 x 1024 forward, for context; nos: number of states "
-                         "and bin-averaged DOS at the headline shape")
+                         "and bin-averaged DOS at the headline shape; chi: susceptibility spectral weight at the "
+                         "headline model")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device-to-device copy of 256 MiB (5 times) to scale HBM byte counters")
     args = ap.parse_args()
@@ -656,6 +718,8 @@ def main():
         return bench_paper_shape(args, torch, tetra, dev)
     if args.workload == "nos":
         return bench_nos(args, torch, tetra, dev)
+    if args.workload == "chi":
+        return bench_chi(args, torch, tetra, dev)
     c = synth.config(WORKLOAD)
     grid, norb, ne = c["grid"], c["norb"], c["ne"]
     eps_np, w_np = synth.band_structure(norb, c["seed"], grid)

@@ -237,6 +237,35 @@ tetra_status tetra_nos_forward(const tetra_desc* d, const float* eps, const void
 tetra_status tetra_dos_binned(const tetra_desc* d, const float* eps, const void* w, int wtype,
                               const float* w_scale, float* dos, unsigned flags, void* stream);
 
+/*
+ * Orbital-resolved susceptibility spectral weight: the imaginary part of the bare (Lindhard)
+ * susceptibility at zero temperature for a transfer q on the k-grid, by the linear tetrahedron method
+ * (the paper names susceptibilities as the next application of its method, Sec. I and Sec. V):
+ *
+ *   out[j][m] = S_m(q, w_j) = sum over tetrahedra of Table I and band pairs (n, n') of
+ *     (1/V_G) int_T W_m [theta(E_F - eps) theta(eps' - E_F) - theta(eps - E_F) theta(E_F - eps')]
+ *                       delta(w_j - (eps' - eps)) d^3k,
+ *
+ * with eps = eps_n(k), eps' = eps_n'(k + q), W_m = b_mn(k) b_mn'(k + q), each linear inside a
+ * tetrahedron between its corner values, the step functions applied exactly (each tetrahedron is
+ * clipped at eps = E_F and eps' = E_F into sub-tetrahedra, each of which takes the corner weights of
+ * Sec. II.C with eps' - eps as its energy). Im chi_0(q, w) = -pi S(q, w) for
+ * chi_0 = (1/N) sum [f(eps) - f(eps')] / (w + eps - eps' + i0); S is per energy unit per k-point,
+ * no spin factor; positive for w > 0 (transitions from occupied n to empty n'), negative for w < 0.
+ *   d        host descriptor; its energy grid (e0, de, ne) is the transfer-energy grid w_j = e0 + j*de
+ *   q1,q2,q3 transfer in grid steps along the three axes (any sign; periodic)
+ *   e_fermi  Fermi energy (finite)
+ *   eps, w, wtype, w_scale   as for tetra_dos_forward (FP32, FP16 with scale, or complex amplitudes)
+ *   out      device, float [ne][norb], overwritten
+ *   flags    TETRA_TILE(shape) or 0 (TETRA_EXACT and TETRA_DETERMINISTIC give TETRA_ERR_UNSUPPORTED)
+ * One workgroup per (tile, band pair): nb*nb*(tiles) must stay below 2^31 (TETRA_ERR_UNSUPPORTED).
+ * A tetrahedron with a non-finite corner energy in either band contributes nothing for that pair.
+ * Allocates nothing.
+ */
+tetra_status tetra_chi_spectral(const tetra_desc* d, int q1, int q2, int q3, float e_fermi, const float* eps,
+                                const void* w, int wtype, const float* w_scale, float* out, unsigned flags,
+                                void* stream);
+
 /* One problem of a batch: its descriptor and device buffers (same meaning as tetra_dos_forward). */
 typedef struct {
   tetra_desc d;

@@ -174,7 +174,8 @@ def tet_chi(e, ep, W, ef, E, vol):
 
 def chi(eps, w, grid, q, ef, w0, dw, nw, nthreads=None):
     """FP64 orbital-resolved susceptibility spectral weight ``S[nw, norb]`` at w_j = w0 + j*dw for the
-    transfer ``q`` (grid steps), Fermi energy ``ef``; and the number of sub-tetrahedra. Im chi_0 = -pi S."""
+    transfer ``q`` (grid steps), Fermi energy ``ef``; and the number of (sub-tetrahedron, band pair,
+    energy) updates in open windows. Im chi_0 = -pi S."""
     eps, w, n1, n2, n3, nb, norb = _grid_args(eps, w, grid)
     out = np.zeros((nw, norb), dtype=np.float64)
     q1, q2, q3 = (int(x) for x in q)

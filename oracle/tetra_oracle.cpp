@@ -592,7 +592,8 @@ double tet_chi(const double e[4], const double ep[4], const double W[4], double 
 
 // Adds one tetrahedron-band-pair's spectral weight at every grid energy inside its sub-tetrahedra's
 // windows: acc[j][m] += S_m(w_j) for the corner weights Wc[c][m] (norb per corner). Returns the
-// number of sub-tetrahedra with positive volume.
+// number of (sub-tetrahedron, energy) pairs visited, i.e. with the energy strictly inside the
+// sub-tetrahedron's range of eps' - eps.
 int chi_accumulate(const Grid& g, const double e[4], const double ep[4], const double* Wc, double ef, double vol,
                    double* acc) {
   const int norb = g.norb;
@@ -609,7 +610,6 @@ int chi_accumulate(const Grid& g, const double e[4], const double ep[4], const d
     for (const BaryTet& t : subs) {
       const double frac = bary_volume_fraction(t);
       if (!(frac > 0.0)) continue;
-      ++nsub;
       double d[4], ds[4];
       int perm[4];
       for (int i = 0; i < 4; ++i) {
@@ -622,6 +622,7 @@ int chi_accumulate(const Grid& g, const double e[4], const double ep[4], const d
         if (E >= ds[3]) break;
         double wl[4], gl[4];
         corner_weights<double>(ds, E, vol * frac / 4.0, wl, gl);
+        ++nsub;
         for (int m = 0; m < norb; ++m) {
           double s = 0.0;
           for (int l = 0; l < 4; ++l) {
@@ -656,7 +657,8 @@ double tetra_oracle_tet_chi(const double e[4], const double ep[4], const double 
 //   eps [nb][nk] FP32, w [nb][norb][nk] FP32 (b = |a|^2), host memory.
 // Sums over every band pair (n, n'). A tetrahedron with a non-finite corner energy in either band
 // contributes nothing. Slabs of constant i1 with one partial each, reduced in slab order. Returns
-// the number of sub-tetrahedra with positive volume, or -1 on invalid arguments.
+// the number of (sub-tetrahedron, band pair, energy) updates inside the sub-tetrahedra's open
+// windows, or -1 on invalid arguments.
 long long tetra_oracle_chi(int n1, int n2, int n3, int nb, int norb, int q1, int q2, int q3, double ef,
                            double w0, double dw, int nw, const float* eps, const float* w, double* out,
                            int nthreads) {

@@ -31,6 +31,7 @@ __all__ = [
     "backward_workspace_bytes",
     "nos_forward",
     "dos_binned",
+    "chi_spectral",
     "dos",
     "dos_batched",
     "batched_workspace_bytes",
@@ -125,6 +126,8 @@ def lib():
         L.tetra_nos_forward.restype = i
         L.tetra_dos_binned.argtypes = [ctypes.POINTER(TetraDesc), p, p, i, p, p, u, p]
         L.tetra_dos_binned.restype = i
+        L.tetra_chi_spectral.argtypes = [ctypes.POINTER(TetraDesc), i, i, i, ctypes.c_float, p, p, i, p, p, u, p]
+        L.tetra_chi_spectral.restype = i
         L.tetra_dos_backward.argtypes = [ctypes.POINTER(TetraDesc), p, p, i, p, p, p, p, u, p]
         L.tetra_dos_backward.restype = i
         L.tetra_dos_backward_workspace.argtypes = [ctypes.POINTER(TetraDesc), u]
@@ -248,6 +251,29 @@ def dos_binned(eps, w, grid, e0, de, ne, *, w_scale=None, out=None, tile=None):
     number of states gained across the bin of width de centred on E_j, divided by de. Arguments as
     for ``dos_forward``."""
     return _integrated("tetra_dos_binned", eps, w, grid, e0, de, ne, w_scale, out, tile)
+
+
+def chi_spectral(eps, w, grid, q, e_fermi, w0, dw, nw, *, w_scale=None, out=None, tile=None):
+    """Orbital-resolved susceptibility spectral weight ``S [nw, norb]`` (FP32) at transfer energies
+    w_j = w0 + j*dw for the transfer ``q`` (three integers, grid steps) and Fermi energy ``e_fermi``:
+    the imaginary part of the bare Lindhard susceptibility at zero temperature is ``-pi S``. Sums every
+    band pair (n, n') with weights b_n(k) b_n'(k + q). Arguments otherwise as for ``dos_forward``."""
+    torch = _torch()
+    nk, nb, norb = _shapes(eps, w, grid)
+    dev = eps.device
+    _require(eps, "eps", (nb, nk), (torch.float32,), dev)
+    _require(w, "w", (nb, norb, nk), _weight_dtypes(torch), dev)
+    wtype = _weights_type(torch, w, w_scale, nb, dev)
+    if out is None:
+        out = torch.empty((int(nw), norb), dtype=torch.float32, device=dev)
+    _require(out, "out", (int(nw), norb), (torch.float32,), dev)
+    q1, q2, q3 = (int(x) for x in q)
+    d = make_desc(grid, nb, norb, w0, dw, nw)
+    st = lib().tetra_chi_spectral(ctypes.byref(d), q1, q2, q3, float(e_fermi), eps.data_ptr(), w.data_ptr(), wtype,
+                                  w_scale.data_ptr() if w_scale is not None else None, out.data_ptr(),
+                                  _tile_flag(tile), _stream_handle(dev))
+    _check("tetra_chi_spectral", st)
+    return out
 
 
 def _check_workspace(workspace, need, dev):

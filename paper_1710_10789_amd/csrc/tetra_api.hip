@@ -199,6 +199,23 @@ tetra_status tetra_dos_binned(const tetra_desc* d, const float* eps, const void*
   return nos_entry(d, eps, w, wtype, w_scale, dos, flags, stream, true);
 }
 
+tetra_status tetra_chi_spectral(const tetra_desc* d, int q1, int q2, int q3, float e_fermi, const float* eps,
+                                const void* w, int wtype, const float* w_scale, float* out, unsigned flags,
+                                void* stream) {
+  tetra_status st = check_desc(d);
+  if (st != TETRA_OK) return st;
+  if (!eps || !w || !out) return TETRA_ERR_ARG;
+  if ((st = check_weights(wtype, w_scale)) != TETRA_OK) return st;
+  if (!std::isfinite(e_fermi)) return TETRA_ERR_ARG;
+  if (flags & ~(unsigned)(TETRA_EXACT | TETRA_DETERMINISTIC | TETRA_TILE_MASK)) return TETRA_ERR_ARG;
+  const int shape = (int)((flags & TETRA_TILE_MASK) >> 8);
+  if (shape >= tetra::kTileShapes) return TETRA_ERR_ARG;
+  if (flags & (TETRA_EXACT | TETRA_DETERMINISTIC)) return TETRA_ERR_UNSUPPORTED;
+  if (tetra::chi_units(*d, shape) > 2147483647 - 8) return TETRA_ERR_UNSUPPORTED;  // one workgroup per unit
+  return hip_status(tetra::chi(*d, q1, q2, q3, e_fermi, eps, w, wtype, scale_of(wtype, w_scale), out, shape,
+                               (hipStream_t)stream));
+}
+
 size_t tetra_dos_batched_workspace(const tetra_item* items, int n, int wtype, unsigned flags) {
   if (!items || n < 1 || (wtype != TETRA_W_F32 && wtype != TETRA_W_F16 && wtype != TETRA_W_C32) || flags != 0)
     return 0;

@@ -1,0 +1,386 @@
+// Susceptibility kernel: orbital-resolved imaginary part of the bare (Lindhard) susceptibility at zero
+// temperature for a transfer q on the k-grid, as the spectral weight S_m(q, w) of tetra_chi_device.h
+// (Im chi_0 = -pi S), by the linear tetrahedron method of Guterding & Jeschke (arXiv:1710.10789,
+// Sec. II) with the difference energy eps_n'(k + q) - eps_n(k) in the role of the band energy.
+//
+// Work decomposition, as the DOS forward: one workgroup per (tile of TX x TY x TZ cubes, band pair
+// (n, n')), one lane per cube looping over the six tetrahedra of Table I. The tile's grid points are
+// staged in LDS with eps_n at the point, eps_n' at the point shifted by q (periodic), and the product
+// weights W_m = b_mn(k) b_mn'(k + q). Per (tetrahedron, band pair) and occupation region, the
+// tetrahedron is clipped at eps = E_F and eps' = E_F into at most nine sub-tetrahedra (recomputed
+// piece by piece, nothing stored); each takes the DOS treatment of the forward kernel (sort, exact
+// window, case split, corner weights of Sec. II.C), its corner weights are mapped back to the parent's
+// corners through its barycentric coordinates and contracted with the corner weights W. Contributions
+// have both signs (the two regions), so the LDS histogram holds 64-bit two's-complement fixed point
+// with a power-of-two scale from a bound: the part of a tetrahedron on either side of an occupation
+// boundary has a section no larger than the whole tetrahedron's, so a tetrahedron adds at most
+// 12 V max|W| / (max - min of eps' - eps) to any bin (V = V_T/(4 V_G)). One global float atomic per
+// touched (energy, orbital) bin at the end.
+
+#include "tetra_chi_device.h"
+#include "tetra_device.h"
+#include "tetra_internal.h"
+#include "tetra_weights.h"
+
+namespace tetra {
+
+namespace {
+
+constexpr int NT = kTileCubes;
+constexpr int NPMAX = kTilePointsMax;
+constexpr int HCAP = 2048;  // LDS histogram capacity in 64-bit words
+constexpr int NXCD = 8;
+
+struct ChiArgs {
+  const float* eps;
+  const void* w;
+  const float* w_scale;
+  float* out;
+  int n1, n2, n3, nb, ne;
+  int q1, q2, q3;  // transfer in grid steps, reduced to [0, n)
+  float ef, e0, de, inv_de, V;
+  int TX, TY, TZ;
+  int t1, t2, t3, ntiles, nunits, per_xcd;
+};
+
+__device__ __forceinline__ int wrap_index(int v, int n) {
+  if (v >= n) v -= n;
+  if (v >= n) v %= n;
+  return v;
+}
+
+__device__ __forceinline__ float wave_min_f(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ float wave_max_f(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ float wave_sum_f(float v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+template <int NORB, typename WT>
+__global__ __launch_bounds__(NT) void chi_kernel(ChiArgs a) {
+  constexpr int RS = (HCAP / NORB - 1) | 1;  // histogram row stride (one row per orbital), odd
+  __shared__ float s_e[NPMAX];
+  __shared__ float s_ep[NPMAX];
+  __shared__ float s_W[NPMAX * NORB];
+  __shared__ unsigned long long s_hist[HCAP];
+  __shared__ float s_red[7 * (NT / 64)];
+
+  const int b = blockIdx.x;
+  const int unit = (b % NXCD) * a.per_xcd + b / NXCD;
+  if (unit >= a.nunits) return;
+  const int pair = unit / a.ntiles;
+  const int tile = unit - pair * a.ntiles;
+  const int n = pair / a.nb, np = pair - n * a.nb;
+  const int TX = a.TX, TY = a.TY, TZ = a.TZ;
+  const int PY = TY + 1, PZ = TZ + 1;
+  const int NP = (TX + 1) * PY * PZ;
+  const int tz = tile % a.t3;
+  const int ty = (tile / a.t3) % a.t2;
+  const int tx = tile / (a.t3 * a.t2);
+  const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+  const int tid = threadIdx.x;
+  const int64_t nk = (int64_t)a.n1 * a.n2 * a.n3;
+  const float* eps_n = a.eps + (int64_t)n * nk;
+  const float* eps_p = a.eps + (int64_t)np * nk;
+  const WT* w_n = static_cast<const WT*>(a.w) + (int64_t)n * NORB * nk;
+  const WT* w_p = static_cast<const WT*>(a.w) + (int64_t)np * NORB * nk;
+  const float sc_n = a.w_scale ? a.w_scale[n] : 1.0f, sc_p = a.w_scale ? a.w_scale[np] : 1.0f;
+
+  // Stage the tile: eps_n at the point, eps_n' at the point + q, W = b_n(k) b_n'(k + q); reduce the
+  // ranges of eps, eps', eps' - eps and the largest |W|.
+  float r_emin = __builtin_huge_valf(), r_emax = -__builtin_huge_valf();
+  float r_pmin = __builtin_huge_valf(), r_pmax = -__builtin_huge_valf();
+  float r_dmin = __builtin_huge_valf(), r_dmax = -__builtin_huge_valf(), r_wmax = 0.0f;
+  for (int p = tid; p < NP; p += NT) {
+    const int pz = p % PZ, py = (p / PZ) % PY, px = p / (PZ * PY);
+    const int i1 = wrap_index(x0 + px, a.n1), i2 = wrap_index(y0 + py, a.n2), i3 = wrap_index(z0 + pz, a.n3);
+    const int64_t k = ((int64_t)i1 * a.n2 + i2) * a.n3 + i3;
+    const int64_t kq = ((int64_t)wrap_index(i1 + a.q1, a.n1) * a.n2 + wrap_index(i2 + a.q2, a.n2)) * a.n3 +
+                       wrap_index(i3 + a.q3, a.n3);
+    const float e = eps_n[k], ep = eps_p[kq];
+    s_e[p] = e;
+    s_ep[p] = ep;
+    if (__builtin_isfinite(e) && __builtin_isfinite(ep)) {
+      r_emin = fminf(r_emin, e);
+      r_emax = fmaxf(r_emax, e);
+      r_pmin = fminf(r_pmin, ep);
+      r_pmax = fmaxf(r_pmax, ep);
+      r_dmin = fminf(r_dmin, ep - e);
+      r_dmax = fmaxf(r_dmax, ep - e);
+    }
+#pragma unroll
+    for (int m = 0; m < NORB; ++m) {
+      const float W = weight_value(w_n[(int64_t)m * nk + k], sc_n) * weight_value(w_p[(int64_t)m * nk + kq], sc_p);
+      s_W[p * NORB + m] = W;
+      r_wmax = fmaxf(r_wmax, fabsf(W));
+    }
+  }
+  float red[7] = {wave_min_f(r_emin), wave_max_f(r_emax), wave_min_f(r_pmin), wave_max_f(r_pmax),
+                  wave_min_f(r_dmin), wave_max_f(r_dmax), wave_max_f(r_wmax)};
+  if ((tid & 63) == 0)
+#pragma unroll
+    for (int i = 0; i < 7; ++i) s_red[i * (NT / 64) + (tid >> 6)] = red[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+    float v = s_red[i * (NT / 64)];
+#pragma unroll
+    for (int wv = 1; wv < NT / 64; ++wv) {
+      const float x = s_red[i * (NT / 64) + wv];
+      v = (i == 0 || i == 2 || i == 4) ? fminf(v, x) : fmaxf(v, x);
+    }
+    red[i] = v;
+  }
+  const float ef = a.ef;
+  if (!(red[4] <= red[5])) return;  // no finite pair in this tile (uniform across the block)
+  if (!region_possible(0, red[0], red[1], red[2], red[3], ef) && !region_possible(1, red[0], red[1], red[2], red[3], ef))
+    return;
+  int J0, J1;
+  range_window(red[4], red[5], a.e0, a.inv_de, a.ne, J0, J1);
+  if (J0 > J1) return;
+  const float wmax = red[6];
+
+  const int cz = tid % TZ, cy = (tid / TZ) % TY, cx = tid / (TZ * TY);
+  const bool valid = (x0 + cx < a.n1) && (y0 + cy < a.n2) && (z0 + cz < a.n3);
+  const int pbase = (cx * PY + cy) * PZ + cz;
+  auto point_offset = [PY, PZ](int s) { return (s & 1) * (PY * PZ) + ((s >> 1) & 1) * PZ + (s >> 2); };
+
+  // Corner data of tetrahedron t of this lane's cube; false when it cannot contribute to [lo, hi].
+  auto corners = [&](int t, int lo, int hi, int pt[4], float e[4], float ep[4], bool reg[2]) {
+    const uint32_t slots = tet_slots(t);
+    float emin = __builtin_huge_valf(), emax = -emin, pmin = emin, pmax = -emin, dmin = emin, dmax = -emin;
+    bool fin = true;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      pt[l] = pbase + point_offset((slots >> (4 * l)) & 7);
+      e[l] = s_e[pt[l]];
+      ep[l] = s_ep[pt[l]];
+      fin = fin && __builtin_isfinite(e[l]) && __builtin_isfinite(ep[l]);
+      emin = fminf(emin, e[l]);
+      emax = fmaxf(emax, e[l]);
+      pmin = fminf(pmin, ep[l]);
+      pmax = fmaxf(pmax, ep[l]);
+      dmin = fminf(dmin, ep[l] - e[l]);
+      dmax = fmaxf(dmax, ep[l] - e[l]);
+    }
+    if (!fin || !(dmax > dmin)) return false;
+    reg[0] = region_possible(0, emin, emax, pmin, pmax, ef);
+    reg[1] = region_possible(1, emin, emax, pmin, pmax, ef);
+    if (!reg[0] && !reg[1]) return false;
+    int jlo, jhi;
+    energy_window(dmin, dmax, a.e0, a.inv_de, lo, hi, jlo, jhi);
+    return jlo <= jhi + 2;
+  };
+
+  // Bound on any bin's |sum|: sum over tetrahedra that may contribute of 12 V max|W| / (dmax - dmin).
+  float bound = 0.0f;
+  if (valid) {
+#pragma unroll 1
+    for (int t = 0; t < 6; ++t) {
+      int pt[4];
+      float e[4], ep[4];
+      bool reg[2];
+      if (!corners(t, J0, J1, pt, e, ep, reg)) continue;
+      float dmin = ep[0] - e[0], dmax = dmin;
+#pragma unroll
+      for (int l = 1; l < 4; ++l) {
+        dmin = fminf(dmin, ep[l] - e[l]);
+        dmax = fmaxf(dmax, ep[l] - e[l]);
+      }
+      bound += 12.0f * a.V * wmax * rcp(dmax - dmin);
+    }
+  }
+  bound = wave_sum_f(fminf(bound, 1.0e37f));
+  __syncthreads();  // every lane has read s_red
+  if ((tid & 63) == 0) s_red[tid >> 6] = bound;
+  __syncthreads();
+  float B = 0.0f;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) B += s_red[i];
+  if (!(B > 0.0f)) return;  // nothing to add (uniform across the block)
+  int bexp;
+  frexpf(fminf(B, 3.0e38f), &bexp);  // B <= 2^bexp
+  const int sexp = min(62 - bexp, 126);
+  const float VS = a.V * ldexpf(1.0f, sexp);  // V_T/(4 V_G) in units of the fixed point, B * S <= 2^62
+  const double inv_S = ldexp(1.0, -sexp);
+
+  for (int c0 = J0; c0 <= J1; c0 += RS) {
+    const int c1 = min(c0 + RS - 1, J1);
+    const int L = c1 - c0 + 1;
+    for (int q = tid; q < NORB * L; q += NT) {
+      const int m = q / L;
+      s_hist[m * RS + (q - m * L)] = 0ull;
+    }
+    __syncthreads();
+    if (valid) {
+#pragma unroll 1
+      for (int t = 0; t < 6; ++t) {
+        int pt[4];
+        float e[4], ep[4];
+        bool reg[2];
+        if (!corners(t, c0, c1, pt, e, ep, reg)) continue;
+        float bb[4][NORB];
+#pragma unroll
+        for (int l = 0; l < 4; ++l)
+#pragma unroll
+          for (int m = 0; m < NORB; ++m) bb[l][m] = s_W[pt[l] * NORB + m];
+#pragma unroll 1
+        for (int r = 0; r < 2; ++r) {
+          if (!reg[r]) continue;
+          const float sign = r == 0 ? 1.0f : -1.0f;
+          float f1c[4], f2c[4], P[4][4], f1[4];
+          region_planes(r, e, ep, ef, f1c, f2c);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            f1[i] = f1c[i];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) P[i][c] = i == c ? 1.0f : 0.0f;
+          }
+          const int ni1 = inside_first(P, f1);
+#pragma unroll 1
+          for (int ia = 0; ia < clip_pieces(ni1); ++ia) {
+            float A[4][4], f2[4];
+            clip_piece(P, f1, ni1, ia, A);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              f2[i] = __builtin_fmaf(A[i][0], f2c[0], __builtin_fmaf(A[i][1], f2c[1],
+                                     __builtin_fmaf(A[i][2], f2c[2], A[i][3] * f2c[3])));
+            const int ni2 = inside_first(A, f2);
+#pragma unroll 1
+            for (int ib = 0; ib < clip_pieces(ni2); ++ib) {
+              float S[4][4];
+              clip_piece(A, f2, ni2, ib, S);
+              const float frac = sub_volume(S);
+              if (!(frac > 0.0f)) continue;
+              float d[4];
+#pragma unroll
+              for (int i = 0; i < 4; ++i)
+                d[i] = __builtin_fmaf(S[i][0], ep[0] - e[0], __builtin_fmaf(S[i][1], ep[1] - e[1],
+                                      __builtin_fmaf(S[i][2], ep[2] - e[2], S[i][3] * (ep[3] - e[3]))));
+              int tag[4] = {0, 1, 2, 3};
+              bool sw[5];
+              sort4(d, tag, sw);
+              int jlo, jhi;
+              energy_window(d[0], d[3], a.e0, a.inv_de, c0, c1, jlo, jhi);
+              if (jlo > jhi + 2) continue;
+              const float Vs = VS * frac;
+              const TetSetup cs = tet_setup(d, a.e0, Vs);
+              tet_window(cs, a.de, c0, c1, jlo, jhi);
+              if (jlo > jhi) continue;
+              permute_rows(sw, S);
+              int jA, jB;
+              case_split(cs, a.de, a.inv_de, jlo, jhi, jA, jB);
+              float coef[4][4];
+              if (jB > jA) corner_dos_B_coeffs(cs, Vs, coef);
+              for (int j = jlo; j <= jhi; ++j) {
+                float g[4];
+                if (j <= jA) {
+                  corner_dos_A(cs, local_x(cs, j, a.de), g);
+                  g[0] = fmaxf(g[0], 0.0f);
+                } else if (j <= jB) {
+                  corner_dos_B_poly(coef, local_z(cs, j, a.de), g);
+#pragma unroll
+                  for (int l = 0; l < 4; ++l) g[l] = fmaxf(g[l], 0.0f);
+                } else {
+                  corner_dos_C(cs, local_y(cs, j, a.de), g);
+                  g[3] = fmaxf(g[3], 0.0f);
+                }
+                float G[4];
+                parent_weights(S, g, G);
+#pragma unroll
+                for (int l = 0; l < 4; ++l) G[l] *= sign;
+                unsigned long long* h = &s_hist[j - c0];
+#pragma unroll
+                for (int m = 0; m < NORB; ++m) {
+                  const float v = __builtin_fmaf(G[0], bb[0][m], __builtin_fmaf(G[1], bb[1][m],
+                                                 __builtin_fmaf(G[2], bb[2][m], G[3] * bb[3][m])));
+                  atomicAdd(&h[m * RS], (unsigned long long)__float2ll_rn(v));
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    for (int q = tid; q < L * NORB; q += NT) {
+      const int rr = q / NORB, m = q - rr * NORB;
+      const long long v = (long long)s_hist[m * RS + rr];
+      if (v != 0) unsafeAtomicAdd(&a.out[(int64_t)(c0 + rr) * NORB + m], (float)((double)v * inv_S));
+    }
+    __syncthreads();
+  }
+}
+
+template <int NORB>
+hipError_t launch_chi(const ChiArgs& a, int wtype, int grid, hipStream_t s) {
+  if (wtype == TETRA_W_F16)
+    hipLaunchKernelGGL((chi_kernel<NORB, _Float16>), dim3(grid), dim3(NT), 0, s, a);
+  else if (wtype == TETRA_W_C32)
+    hipLaunchKernelGGL((chi_kernel<NORB, float2>), dim3(grid), dim3(NT), 0, s, a);
+  else
+    hipLaunchKernelGGL((chi_kernel<NORB, float>), dim3(grid), dim3(NT), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int64_t chi_units(const tetra_desc& d, int shape) {
+  const TileShape sh = tile_shape(shape);
+  const int64_t ntiles = (int64_t)((d.n1 + sh.x - 1) / sh.x) * ((d.n2 + sh.y - 1) / sh.y) * ((d.n3 + sh.z - 1) / sh.z);
+  return ntiles * d.nb * d.nb;
+}
+
+hipError_t chi(const tetra_desc& d, int q1, int q2, int q3, float e_fermi, const float* eps, const void* w, int wtype,
+               const float* w_scale, float* out, int shape, hipStream_t s) {
+  ChiArgs a;
+  a.eps = eps;
+  a.w = w;
+  a.w_scale = w_scale;
+  a.out = out;
+  a.n1 = d.n1;
+  a.n2 = d.n2;
+  a.n3 = d.n3;
+  a.nb = d.nb;
+  a.ne = d.ne;
+  a.q1 = ((q1 % d.n1) + d.n1) % d.n1;
+  a.q2 = ((q2 % d.n2) + d.n2) % d.n2;
+  a.q3 = ((q3 % d.n3) + d.n3) % d.n3;
+  a.ef = e_fermi;
+  a.e0 = d.e0;
+  a.de = d.de;
+  a.inv_de = 1.0f / d.de;
+  a.V = (float)(1.0 / (24.0 * (double)d.n1 * d.n2 * d.n3));
+  const TileShape sh = tile_shape(shape);
+  a.TX = sh.x;
+  a.TY = sh.y;
+  a.TZ = sh.z;
+  a.t1 = (d.n1 + sh.x - 1) / sh.x;
+  a.t2 = (d.n2 + sh.y - 1) / sh.y;
+  a.t3 = (d.n3 + sh.z - 1) / sh.z;
+  a.ntiles = a.t1 * a.t2 * a.t3;
+  a.nunits = (int)chi_units(d, shape);
+  a.per_xcd = (a.nunits + NXCD - 1) / NXCD;
+  const int grid = a.per_xcd * NXCD;
+  hipError_t e = fill_zero(out, (int64_t)d.ne * d.norb, s);
+  if (e != hipSuccess) return e;
+  switch (d.norb) {
+#define TETRA_CASE(N) \
+  case N:             \
+    return launch_chi<N>(a, wtype, grid, s);
+    TETRA_CASE(1) TETRA_CASE(2) TETRA_CASE(3) TETRA_CASE(4) TETRA_CASE(5) TETRA_CASE(6) TETRA_CASE(7)
+    TETRA_CASE(8) TETRA_CASE(9) TETRA_CASE(10) TETRA_CASE(11) TETRA_CASE(12) TETRA_CASE(13)
+    TETRA_CASE(14) TETRA_CASE(15) TETRA_CASE(16)
+#undef TETRA_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace tetra

@@ -50,4 +50,10 @@ size_t backward_workspace_bytes(const tetra_desc& d, int shape);
 hipError_t backward(const tetra_desc& d, const float* eps, const void* w, int wtype, const float* w_scale,
                     const float* G, float* grad_eps, float* grad_w, int shape, void* workspace, hipStream_t s);
 
+// Susceptibility spectral weight into out[ne][norb] (the energy grid of d is the transfer-energy
+// grid) for the transfer (q1, q2, q3) in grid steps and Fermi energy e_fermi; every band pair.
+int64_t chi_units(const tetra_desc& d, int shape);
+hipError_t chi(const tetra_desc& d, int q1, int q2, int q3, float e_fermi, const float* eps, const void* w, int wtype,
+               const float* w_scale, float* out, int shape, hipStream_t s);
+
 }  // namespace tetra

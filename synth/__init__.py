@@ -21,6 +21,7 @@ from .tb import (
     amplitudes,
     band_structure,
     energy_grid,
+    chi_grid,
     cosine_band,
     separable_band,
     CONFIGS,
@@ -34,6 +35,7 @@ __all__ = [
     "amplitudes",
     "band_structure",
     "energy_grid",
+    "chi_grid",
     "cosine_band",
     "separable_band",
     "CONFIGS",

@@ -182,7 +182,20 @@ CONFIGS = {
     "k64_b8_e500_fit": dict(grid=(64, 64, 64), norb=8, ne=500, seed=0, target_seed=1),
     # the paper's largest benchmark shape (60 x 60 x 10 k-points, 8 bands, 1024 energies), context only
     "k60x60x10_b8_e1024": dict(grid=(60, 60, 10), norb=8, ne=1024, seed=0),
+    # susceptibility case: the headline model, transfer q = (16, 16, 0) grid steps, 500 transfer energies
+    # from 0 to the band width, Fermi energy at half filling
+    "chi_k64_b8_w500": dict(grid=(64, 64, 64), norb=8, nw=500, seed=0, q=(16, 16, 0)),
 }
+
+
+def chi_grid(eps, nw: int):
+    """``(e_fermi, w0, dw)`` of a susceptibility workload: the Fermi energy at half filling (the median
+    of the finite band energies) and transfer energies w_j = w0 + j*dw from 0 to the band width, all
+    exactly FP32-representable."""
+    fin = eps[np.isfinite(eps)]
+    ef = float(np.float32(np.median(fin)))
+    width = float(np.float32(fin.max()) - np.float32(fin.min()))
+    return ef, 0.0, float(np.float32(width / (nw - 1)))
 
 
 def config(name: str):

@@ -155,6 +155,31 @@ def test_noalloc_forward_rejects_before_any_hip_call(L):
     assert _fwd_na(L, bad, flags=1) == -1
 
 
+def test_chi_rejects_bad_arguments(L):
+    f = L.tetra_chi_spectral
+
+    def call(d=None, ef=0.0, eps=FAKE, w=FAKE, wtype=0, scale=None, out=FAKE, flags=0):
+        return f(ctypes.byref(d if d is not None else good()), 1, 0, -1, ef, eps, w, wtype, scale, out, flags, None)
+
+    assert call(ef=float("nan")) == -1
+    assert call(ef=float("inf")) == -1
+    assert call(eps=None) == -1
+    assert call(w=None) == -1
+    assert call(out=None) == -1
+    assert call(wtype=1) == -1  # FP16 weights need their scale
+    assert call(wtype=0, scale=FAKE) == -1
+    assert call(flags=0x40) == -1
+    assert call(flags=7 << 8) == -1
+    assert call(flags=1) == -2  # no exact accumulation here
+    assert call(flags=2) == -2
+    bad = good()
+    bad.de = -1.0
+    assert call(d=bad) == -1
+    many = good()
+    many.n1, many.n2, many.n3, many.nb, many.norb = 64, 64, 64, 8000, 1  # nb^2 x tiles workgroups >= 2^31
+    assert call(d=many) == -2
+
+
 def test_pack_f16_rejects_bad_arguments(L):
     f = L.tetra_pack_f16
     assert f(0, 2, 3, FAKE, FAKE, FAKE, None) == -1
