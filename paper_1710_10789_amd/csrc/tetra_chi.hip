@@ -242,21 +242,41 @@ __global__ __launch_bounds__(NT) void chi_kernel(ChiArgs a) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) P[i][c] = i == c ? 1.0f : 0.0f;
           }
-          const int ni1 = inside_first(P, f1);
+          // The region is often the whole tetrahedron (n occupied and n' empty at every corner): the
+          // sort and the clipping are skipped there.
+          int ni1 = (f1[0] <= 0.0f) + (f1[1] <= 0.0f) + (f1[2] <= 0.0f) + (f1[3] <= 0.0f);
+          if (ni1 > 0 && ni1 < 4) inside_first(P, f1);
 #pragma unroll 1
           for (int ia = 0; ia < clip_pieces(ni1); ++ia) {
             float A[4][4], f2[4];
-            clip_piece(P, f1, ni1, ia, A);
+            if (ni1 == 4) {
+#pragma unroll
+              for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) A[i][c] = P[i][c];
+            } else {
+              clip_piece(P, f1, ni1, ia, A);
+            }
 #pragma unroll
             for (int i = 0; i < 4; ++i)
               f2[i] = __builtin_fmaf(A[i][0], f2c[0], __builtin_fmaf(A[i][1], f2c[1],
                                      __builtin_fmaf(A[i][2], f2c[2], A[i][3] * f2c[3])));
-            const int ni2 = inside_first(A, f2);
+            const int ni2 = (f2[0] <= 0.0f) + (f2[1] <= 0.0f) + (f2[2] <= 0.0f) + (f2[3] <= 0.0f);
+            if (ni2 > 0 && ni2 < 4) inside_first(A, f2);
 #pragma unroll 1
             for (int ib = 0; ib < clip_pieces(ni2); ++ib) {
               float S[4][4];
-              clip_piece(A, f2, ni2, ib, S);
-              const float frac = sub_volume(S);
+              float frac;
+              if (ni2 == 4) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                  for (int c = 0; c < 4; ++c) S[i][c] = A[i][c];
+                frac = ni1 == 4 ? 1.0f : sub_volume(S);
+              } else {
+                clip_piece(A, f2, ni2, ib, S);
+                frac = sub_volume(S);
+              }
               if (!(frac > 0.0f)) continue;
               float d[4];
 #pragma unroll
