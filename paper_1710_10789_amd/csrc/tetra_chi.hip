@@ -10,12 +10,15 @@
 // tetrahedron is clipped at eps = E_F and eps' = E_F into at most nine sub-tetrahedra (recomputed
 // piece by piece, nothing stored); each takes the DOS treatment of the forward kernel (sort, exact
 // window, case split, corner weights of Sec. II.C), its corner weights are mapped back to the parent's
-// corners through its barycentric coordinates and contracted with the corner weights W. Contributions
-// have both signs (the two regions), so the LDS histogram holds 64-bit two's-complement fixed point
-// with a power-of-two scale from a bound: the part of a tetrahedron on either side of an occupation
-// boundary has a section no larger than the whole tetrahedron's, so a tetrahedron adds at most
-// 12 V max|W| / (max - min of eps' - eps) to any bin (V = V_T/(4 V_G)). One global float atomic per
-// touched (energy, orbital) bin at the end.
+// corners through its barycentric coordinates and contracted with the corner weights W. The LDS
+// histograms hold fixed point with a power-of-two scale from a bound: the part of a tetrahedron on
+// either side of an occupation boundary has a section no larger than the whole tetrahedron's, so a
+// tetrahedron adds at most 12 V max|W| / (max - min of eps' - eps) to any bin (V = V_T/(4 V_G)). With
+// non-negative weights each region's terms are non-negative: one histogram per region, two orbitals
+// per 64-bit word; otherwise one signed 64-bit histogram. One global float atomic per touched
+// (energy, orbital) bin at the end.
+
+#include <type_traits>
 
 #include "tetra_chi_device.h"
 #include "tetra_device.h"
@@ -69,7 +72,7 @@ __global__ __launch_bounds__(NT) void chi_kernel(ChiArgs a) {
   __shared__ float s_ep[NPMAX];
   __shared__ float s_W[NPMAX * NORB];
   __shared__ unsigned long long s_hist[HCAP];
-  __shared__ float s_red[7 * (NT / 64)];
+  __shared__ float s_red[8 * (NT / 64)];
 
   const int b = blockIdx.x;
   const int unit = (b % NXCD) * a.per_xcd + b / NXCD;
@@ -96,7 +99,7 @@ __global__ __launch_bounds__(NT) void chi_kernel(ChiArgs a) {
   // ranges of eps, eps', eps' - eps and the largest |W|.
   float r_emin = __builtin_huge_valf(), r_emax = -__builtin_huge_valf();
   float r_pmin = __builtin_huge_valf(), r_pmax = -__builtin_huge_valf();
-  float r_dmin = __builtin_huge_valf(), r_dmax = -__builtin_huge_valf(), r_wmax = 0.0f;
+  float r_dmin = __builtin_huge_valf(), r_dmax = -__builtin_huge_valf(), r_wmax = 0.0f, r_wmin = 0.0f;
   for (int p = tid; p < NP; p += NT) {
     const int pz = p % PZ, py = (p / PZ) % PY, px = p / (PZ * PY);
     const int i1 = wrap_index(x0 + px, a.n1), i2 = wrap_index(y0 + py, a.n2), i3 = wrap_index(z0 + pz, a.n3);
@@ -119,21 +122,22 @@ __global__ __launch_bounds__(NT) void chi_kernel(ChiArgs a) {
       const float W = weight_value(w_n[(int64_t)m * nk + k], sc_n) * weight_value(w_p[(int64_t)m * nk + kq], sc_p);
       s_W[p * NORB + m] = W;
       r_wmax = fmaxf(r_wmax, fabsf(W));
+      r_wmin = fminf(r_wmin, W);
     }
   }
-  float red[7] = {wave_min_f(r_emin), wave_max_f(r_emax), wave_min_f(r_pmin), wave_max_f(r_pmax),
-                  wave_min_f(r_dmin), wave_max_f(r_dmax), wave_max_f(r_wmax)};
+  float red[8] = {wave_min_f(r_emin), wave_max_f(r_emax), wave_min_f(r_pmin), wave_max_f(r_pmax),
+                  wave_min_f(r_dmin), wave_max_f(r_dmax), wave_max_f(r_wmax), wave_min_f(r_wmin)};
   if ((tid & 63) == 0)
 #pragma unroll
-    for (int i = 0; i < 7; ++i) s_red[i * (NT / 64) + (tid >> 6)] = red[i];
+    for (int i = 0; i < 8; ++i) s_red[i * (NT / 64) + (tid >> 6)] = red[i];
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < 7; ++i) {
+  for (int i = 0; i < 8; ++i) {
     float v = s_red[i * (NT / 64)];
 #pragma unroll
     for (int wv = 1; wv < NT / 64; ++wv) {
       const float x = s_red[i * (NT / 64) + wv];
-      v = (i == 0 || i == 2 || i == 4) ? fminf(v, x) : fmaxf(v, x);
+      v = (i == 0 || i == 2 || i == 4 || i == 7) ? fminf(v, x) : fmaxf(v, x);
     }
     red[i] = v;
   }
@@ -144,7 +148,7 @@ __global__ __launch_bounds__(NT) void chi_kernel(ChiArgs a) {
   int J0, J1;
   range_window(red[4], red[5], a.e0, a.inv_de, a.ne, J0, J1);
   if (J0 > J1) return;
-  const float wmax = red[6];
+  const float wmax = red[6], wmin = red[7];
 
   const int cz = tid % TZ, cy = (tid / TZ) % TY, cx = tid / (TZ * TY);
   const bool valid = (x0 + cx < a.n1) && (y0 + cy < a.n2) && (z0 + cz < a.n3);
@@ -179,7 +183,8 @@ __global__ __launch_bounds__(NT) void chi_kernel(ChiArgs a) {
   };
 
   // Bound on any bin's |sum|: sum over tetrahedra that may contribute of 12 V max|W| / (dmax - dmin).
-  float bound = 0.0f;
+  // Narrow tetrahedra (a range of eps' - eps below 2 de) give spikes that make B loose.
+  float bound = 0.0f, narrow = 0.0f;
   if (valid) {
 #pragma unroll 1
     for (int t = 0; t < 6; ++t) {
@@ -193,149 +198,203 @@ __global__ __launch_bounds__(NT) void chi_kernel(ChiArgs a) {
         dmin = fminf(dmin, ep[l] - e[l]);
         dmax = fmaxf(dmax, ep[l] - e[l]);
       }
-      bound += 12.0f * a.V * wmax * rcp(dmax - dmin);
+      const float term = 12.0f * a.V * wmax * rcp(dmax - dmin);
+      bound += term;
+      if (dmax - dmin < 2.0f * a.de) narrow += term;
     }
   }
   bound = wave_sum_f(fminf(bound, 1.0e37f));
+  narrow = wave_sum_f(fminf(narrow, 1.0e37f));
   __syncthreads();  // every lane has read s_red
-  if ((tid & 63) == 0) s_red[tid >> 6] = bound;
+  if ((tid & 63) == 0) {
+    s_red[tid >> 6] = bound;
+    s_red[(NT / 64) + (tid >> 6)] = narrow;
+  }
   __syncthreads();
-  float B = 0.0f;
+  float B = 0.0f, Bn = 0.0f;
 #pragma unroll
-  for (int i = 0; i < NT / 64; ++i) B += s_red[i];
+  for (int i = 0; i < NT / 64; ++i) {
+    B += s_red[i];
+    Bn += s_red[NT / 64 + i];
+  }
   if (!(B > 0.0f)) return;  // nothing to add (uniform across the block)
+  // Packed: within one region every contribution is non-negative when the weights are (corner weights
+  // and barycentric coordinates are), so each region gets a histogram of its own with two orbitals per
+  // 64-bit word as 32-bit fields (B S <= 2^30, no carry between fields) and the result is their
+  // difference. Otherwise one signed 64-bit histogram (B S <= 2^62).
+  const bool packed = wmin >= 0.0f && Bn <= 0.5f * B;  // uniform across the block
   int bexp;
   frexpf(fminf(B, 3.0e38f), &bexp);  // B <= 2^bexp
-  const int sexp = min(62 - bexp, 126);
-  const float VS = a.V * ldexpf(1.0f, sexp);  // V_T/(4 V_G) in units of the fixed point, B * S <= 2^62
+  const int sexp = min((packed ? 30 : 62) - bexp, 126);
+  const float VS = a.V * ldexpf(1.0f, sexp);  // V_T/(4 V_G) in units of the fixed point
   const double inv_S = ldexp(1.0, -sexp);
 
-  for (int c0 = J0; c0 <= J1; c0 += RS) {
-    const int c1 = min(c0 + RS - 1, J1);
-    const int L = c1 - c0 + 1;
-    for (int q = tid; q < NORB * L; q += NT) {
-      const int m = q / L;
-      s_hist[m * RS + (q - m * L)] = 0ull;
-    }
-    __syncthreads();
-    if (valid) {
+  auto passes = [&](auto packed_tag) {
+    constexpr bool PACKED = decltype(packed_tag)::value;
+    constexpr int NPAIR = (NORB + 1) / 2;
+    // rows: packed, one per orbital pair in each region's half of the histogram; wide, one per orbital
+    constexpr int RSP = (HCAP / 2 / NPAIR - 1) | 1;
+    constexpr int RSX = PACKED ? RSP : RS;
+    unsigned long long* hist_m = s_hist + (PACKED ? HCAP / 2 : 0);  // region -1 (packed only)
+    for (int c0 = J0; c0 <= J1; c0 += RSX) {
+      const int c1 = min(c0 + RSX - 1, J1);
+      const int L = c1 - c0 + 1;
+      const int rows = PACKED ? NPAIR : NORB;
+      for (int q = tid; q < rows * L; q += NT) {
+        const int m = q / L;
+        s_hist[m * RSX + (q - m * L)] = 0ull;
+        if (PACKED) hist_m[m * RSX + (q - m * L)] = 0ull;
+      }
+      __syncthreads();
+      if (valid) {
 #pragma unroll 1
-      for (int t = 0; t < 6; ++t) {
-        int pt[4];
-        float e[4], ep[4];
-        bool reg[2];
-        if (!corners(t, c0, c1, pt, e, ep, reg)) continue;
-        float bb[4][NORB];
+        for (int t = 0; t < 6; ++t) {
+          int pt[4];
+          float e[4], ep[4];
+          bool reg[2];
+          if (!corners(t, c0, c1, pt, e, ep, reg)) continue;
+          float bb[4][NORB];
 #pragma unroll
-        for (int l = 0; l < 4; ++l)
+          for (int l = 0; l < 4; ++l)
 #pragma unroll
-          for (int m = 0; m < NORB; ++m) bb[l][m] = s_W[pt[l] * NORB + m];
+            for (int m = 0; m < NORB; ++m) bb[l][m] = s_W[pt[l] * NORB + m];
 #pragma unroll 1
-        for (int r = 0; r < 2; ++r) {
-          if (!reg[r]) continue;
-          const float sign = r == 0 ? 1.0f : -1.0f;
-          float f1c[4], f2c[4], P[4][4], f1[4];
-          region_planes(r, e, ep, ef, f1c, f2c);
+          for (int r = 0; r < 2; ++r) {
+            if (!reg[r]) continue;
+            const float sign = r == 0 ? 1.0f : -1.0f;
+            unsigned long long* hreg = (PACKED && r == 1) ? hist_m : s_hist;
+            float f1c[4], f2c[4], P[4][4], f1[4];
+            region_planes(r, e, ep, ef, f1c, f2c);
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            f1[i] = f1c[i];
+            for (int i = 0; i < 4; ++i) {
+              f1[i] = f1c[i];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) P[i][c] = i == c ? 1.0f : 0.0f;
-          }
-          // The region is often the whole tetrahedron (n occupied and n' empty at every corner): the
-          // sort and the clipping are skipped there.
-          int ni1 = (f1[0] <= 0.0f) + (f1[1] <= 0.0f) + (f1[2] <= 0.0f) + (f1[3] <= 0.0f);
-          if (ni1 > 0 && ni1 < 4) inside_first(P, f1);
-#pragma unroll 1
-          for (int ia = 0; ia < clip_pieces(ni1); ++ia) {
-            float A[4][4], f2[4];
-            if (ni1 == 4) {
-#pragma unroll
-              for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) A[i][c] = P[i][c];
-            } else {
-              clip_piece(P, f1, ni1, ia, A);
+              for (int c = 0; c < 4; ++c) P[i][c] = i == c ? 1.0f : 0.0f;
             }
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-              f2[i] = __builtin_fmaf(A[i][0], f2c[0], __builtin_fmaf(A[i][1], f2c[1],
-                                     __builtin_fmaf(A[i][2], f2c[2], A[i][3] * f2c[3])));
-            const int ni2 = (f2[0] <= 0.0f) + (f2[1] <= 0.0f) + (f2[2] <= 0.0f) + (f2[3] <= 0.0f);
-            if (ni2 > 0 && ni2 < 4) inside_first(A, f2);
+            // The region is often the whole tetrahedron (n occupied and n' empty at every corner): the
+            // sort and the clipping are skipped there.
+            const int ni1 = (f1[0] <= 0.0f) + (f1[1] <= 0.0f) + (f1[2] <= 0.0f) + (f1[3] <= 0.0f);
+            if (ni1 > 0 && ni1 < 4) inside_first(P, f1);
 #pragma unroll 1
-            for (int ib = 0; ib < clip_pieces(ni2); ++ib) {
-              float S[4][4];
-              float frac;
-              if (ni2 == 4) {
+            for (int ia = 0; ia < clip_pieces(ni1); ++ia) {
+              float A[4][4], f2[4];
+              if (ni1 == 4) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
 #pragma unroll
-                  for (int c = 0; c < 4; ++c) S[i][c] = A[i][c];
-                frac = ni1 == 4 ? 1.0f : sub_volume(S);
+                  for (int c = 0; c < 4; ++c) A[i][c] = P[i][c];
               } else {
-                clip_piece(A, f2, ni2, ib, S);
-                frac = sub_volume(S);
+                clip_piece(P, f1, ni1, ia, A);
               }
-              if (!(frac > 0.0f)) continue;
-              float d[4];
 #pragma unroll
               for (int i = 0; i < 4; ++i)
-                d[i] = __builtin_fmaf(S[i][0], ep[0] - e[0], __builtin_fmaf(S[i][1], ep[1] - e[1],
-                                      __builtin_fmaf(S[i][2], ep[2] - e[2], S[i][3] * (ep[3] - e[3]))));
-              int tag[4] = {0, 1, 2, 3};
-              bool sw[5];
-              sort4(d, tag, sw);
-              int jlo, jhi;
-              energy_window(d[0], d[3], a.e0, a.inv_de, c0, c1, jlo, jhi);
-              if (jlo > jhi + 2) continue;
-              const float Vs = VS * frac;
-              const TetSetup cs = tet_setup(d, a.e0, Vs);
-              tet_window(cs, a.de, c0, c1, jlo, jhi);
-              if (jlo > jhi) continue;
-              permute_rows(sw, S);
-              int jA, jB;
-              case_split(cs, a.de, a.inv_de, jlo, jhi, jA, jB);
-              float coef[4][4];
-              if (jB > jA) corner_dos_B_coeffs(cs, Vs, coef);
-              for (int j = jlo; j <= jhi; ++j) {
-                float g[4];
-                if (j <= jA) {
-                  corner_dos_A(cs, local_x(cs, j, a.de), g);
-                  g[0] = fmaxf(g[0], 0.0f);
-                } else if (j <= jB) {
-                  corner_dos_B_poly(coef, local_z(cs, j, a.de), g);
+                f2[i] = __builtin_fmaf(A[i][0], f2c[0], __builtin_fmaf(A[i][1], f2c[1],
+                                       __builtin_fmaf(A[i][2], f2c[2], A[i][3] * f2c[3])));
+              const int ni2 = (f2[0] <= 0.0f) + (f2[1] <= 0.0f) + (f2[2] <= 0.0f) + (f2[3] <= 0.0f);
+              if (ni2 > 0 && ni2 < 4) inside_first(A, f2);
+#pragma unroll 1
+              for (int ib = 0; ib < clip_pieces(ni2); ++ib) {
+                float S[4][4];
+                float frac;
+                if (ni2 == 4) {
 #pragma unroll
-                  for (int l = 0; l < 4; ++l) g[l] = fmaxf(g[l], 0.0f);
+                  for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) S[i][c] = A[i][c];
+                  frac = ni1 == 4 ? 1.0f : sub_volume(S);
                 } else {
-                  corner_dos_C(cs, local_y(cs, j, a.de), g);
-                  g[3] = fmaxf(g[3], 0.0f);
+                  clip_piece(A, f2, ni2, ib, S);
+                  frac = sub_volume(S);
                 }
-                float G[4];
-                parent_weights(S, g, G);
+                if (!(frac > 0.0f)) continue;
+                float d[4];
 #pragma unroll
-                for (int l = 0; l < 4; ++l) G[l] *= sign;
-                unsigned long long* h = &s_hist[j - c0];
+                for (int i = 0; i < 4; ++i)
+                  d[i] = __builtin_fmaf(S[i][0], ep[0] - e[0], __builtin_fmaf(S[i][1], ep[1] - e[1],
+                                        __builtin_fmaf(S[i][2], ep[2] - e[2], S[i][3] * (ep[3] - e[3]))));
+                int tag[4] = {0, 1, 2, 3};
+                bool sw[5];
+                sort4(d, tag, sw);
+                int jlo, jhi;
+                energy_window(d[0], d[3], a.e0, a.inv_de, c0, c1, jlo, jhi);
+                if (jlo > jhi + 2) continue;
+                const float Vs = VS * frac;
+                const TetSetup cs = tet_setup(d, a.e0, Vs);
+                tet_window(cs, a.de, c0, c1, jlo, jhi);
+                if (jlo > jhi) continue;
+                permute_rows(sw, S);
+                int jA, jB;
+                case_split(cs, a.de, a.inv_de, jlo, jhi, jA, jB);
+                float coef[4][4];
+                if (jB > jA) corner_dos_B_coeffs(cs, Vs, coef);
+                for (int j = jlo; j <= jhi; ++j) {
+                  float g[4];
+                  if (j <= jA) {
+                    corner_dos_A(cs, local_x(cs, j, a.de), g);
+                    g[0] = fmaxf(g[0], 0.0f);
+                  } else if (j <= jB) {
+                    corner_dos_B_poly(coef, local_z(cs, j, a.de), g);
 #pragma unroll
-                for (int m = 0; m < NORB; ++m) {
-                  const float v = __builtin_fmaf(G[0], bb[0][m], __builtin_fmaf(G[1], bb[1][m],
-                                                 __builtin_fmaf(G[2], bb[2][m], G[3] * bb[3][m])));
-                  atomicAdd(&h[m * RS], (unsigned long long)__float2ll_rn(v));
+                    for (int l = 0; l < 4; ++l) g[l] = fmaxf(g[l], 0.0f);
+                  } else {
+                    corner_dos_C(cs, local_y(cs, j, a.de), g);
+                    g[3] = fmaxf(g[3], 0.0f);
+                  }
+                  float G[4];
+                  parent_weights(S, g, G);
+                  unsigned long long* h = &hreg[j - c0];
+                  if (PACKED) {
+                    // non-negative terms: the truncating conversion of 1/2 + v rounds (halves up)
+#pragma unroll
+                    for (int pr = 0; pr < NPAIR; ++pr) {
+                      const int m0 = 2 * pr, m1 = 2 * pr + 1;
+                      const float v0 = __builtin_fmaf(G[0], bb[0][m0], __builtin_fmaf(G[1], bb[1][m0],
+                                       __builtin_fmaf(G[2], bb[2][m0], __builtin_fmaf(G[3], bb[3][m0], 0.5f))));
+                      unsigned long long word = (unsigned long long)(unsigned)v0;
+                      if (m1 < NORB) {
+                        const float v1 = __builtin_fmaf(G[0], bb[0][m1], __builtin_fmaf(G[1], bb[1][m1],
+                                         __builtin_fmaf(G[2], bb[2][m1], __builtin_fmaf(G[3], bb[3][m1], 0.5f))));
+                        word |= (unsigned long long)(unsigned)v1 << 32;
+                      }
+                      atomicAdd(&h[pr * RSX], word);
+                    }
+                  } else {
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) G[l] *= sign;
+#pragma unroll
+                    for (int m = 0; m < NORB; ++m) {
+                      const float v = __builtin_fmaf(G[0], bb[0][m], __builtin_fmaf(G[1], bb[1][m],
+                                                     __builtin_fmaf(G[2], bb[2][m], G[3] * bb[3][m])));
+                      atomicAdd(&h[m * RSX], (unsigned long long)__float2ll_rn(v));
+                    }
+                  }
                 }
               }
             }
           }
         }
       }
+      __syncthreads();
+      for (int q = tid; q < L * NORB; q += NT) {
+        const int rr = q / NORB, m = q - rr * NORB;
+        double v;
+        if (PACKED) {
+          const unsigned long long wp = s_hist[(m >> 1) * RSX + rr], wm = hist_m[(m >> 1) * RSX + rr];
+          const unsigned fp = (m & 1) ? (unsigned)(wp >> 32) : (unsigned)(wp & 0xffffffffull);
+          const unsigned fm = (m & 1) ? (unsigned)(wm >> 32) : (unsigned)(wm & 0xffffffffull);
+          v = (double)fp - (double)fm;
+        } else {
+          v = (double)(long long)s_hist[m * RSX + rr];
+        }
+        if (v != 0.0) unsafeAtomicAdd(&a.out[(int64_t)(c0 + rr) * NORB + m], (float)(v * inv_S));
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    for (int q = tid; q < L * NORB; q += NT) {
-      const int rr = q / NORB, m = q - rr * NORB;
-      const long long v = (long long)s_hist[m * RS + rr];
-      if (v != 0) unsafeAtomicAdd(&a.out[(int64_t)(c0 + rr) * NORB + m], (float)((double)v * inv_S));
-    }
-    __syncthreads();
-  }
+  };
+  if (packed)
+    passes(std::true_type{});
+  else
+    passes(std::false_type{});
 }
 
 template <int NORB>

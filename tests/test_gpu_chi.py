@@ -143,3 +143,18 @@ def test_full_size_64cube_8x8_500w(torch_dev, oracle_lib):
     err = dos_err(got, ref)
     print(f"[case] err {err:.3e}, {nsub} updates", flush=True)
     assert err <= 1e-5
+
+
+def test_signed_weights_use_the_signed_accumulator(torch_dev, oracle_lib):
+    """General observables in place of b (negative products W): one signed 64-bit histogram."""
+    rng = np.random.default_rng(31)
+    grid = (7, 6, 5)
+    eps, w = synth.band_structure(3, 17, grid)
+    w = (w * rng.choice([-1.0, 1.0], size=w.shape)).astype(np.float32)
+    ef = float(np.float32(np.median(eps)))
+    w0, dw = _grid_for(eps, 100, True)
+    ref, _ = oracle_lib.chi(eps, w, grid, (2, 3, 1), ef, w0, dw, 100)
+    print("[case] chi signed weights", flush=True)
+    got = _run(torch_dev, eps, w, grid, (2, 3, 1), ef, w0, dw, 100)
+    assert np.abs(ref).max() > 0
+    assert dos_err(got, ref) <= 1e-5
