@@ -45,6 +45,7 @@ KERNEL_SOURCES = {
     "dos_backward_kernel": ("tetra_backward.hip", "tetra_device.h", "tetra_faces.h", "tetra_internal.h",
                             "tetra_weights.h"),
     "nos_kernel": ("tetra_nos.hip", "tetra_nos_device.h", "tetra_device.h", "tetra_internal.h", "tetra_weights.h"),
+    "chi_kernel": ("tetra_chi.hip", "tetra_chi_device.h", "tetra_device.h", "tetra_internal.h", "tetra_weights.h"),
 }
 
 
@@ -244,7 +245,8 @@ def summarize_profiles(kt_dir, fetch_dir=None, write_dir=None, copy_fetch_dir=No
             rd, wt = fe[k] * 1024 * f_fetch, wr[k] * 1024 * f_write
             lines.append(f"| `{k[:90]}` | {fe[k]:.0f} | {wr[k]:.0f} | {rd / 1e6:.2f} | {wt / 1e6:.2f} |")
             for short, pat in (("dos_forward_kernel", "dos_forward_kernel"), ("dos_backward_kernel", "dos_backward_kernel"),
-                               ("dos_backward_kernel", "bwd_gather_kernel"), ("nos_kernel", "nos_kernel")):
+                               ("dos_backward_kernel", "bwd_gather_kernel"), ("nos_kernel", "nos_kernel"),
+                               ("chi_kernel", "chi_kernel")):
                 if pat in k:  # the kernels launched by one call add up (instantiations, gather pass)
                     sha = (source_shas or {}).get(short) or kernel_source_hash(short)
                     rec = traffic.setdefault(short, {"source_sha": sha, "bytes_per_launch": 0.0,
@@ -578,6 +580,7 @@ def bench_chi(args, torch, tetra, dev):
                                "500 transfer energies, E_F at half filling",
                    "dense_updates_per_pass": dense, "tile": list(tetra.TILE_SHAPES[tile])},
         "tile_ms": times,
+        "kernel_source_sha": {"chi_kernel": kernel_source_hash("chi_kernel")},
     }
     if not args.no_cpu_baseline:
         import oracle
@@ -593,7 +596,7 @@ def bench_chi(args, torch, tetra, dev):
         rec["config"]["in_window_updates_per_pass"] = upd
         rec["roofline"] = {"bound": "alu", "kernel": "chi_kernel", "achieved": achieved,
                            "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-                           "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": None,
+                           "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": load_traffic("chi_kernel"),
                            "algorithmic_flops_per_launch": flops, "avg_launch_ms": ms}
         rec["error_vs_fp64_oracle"] = float(np.abs(got - ref).max() / np.abs(ref).max())
         rec["cpu_baseline"] = {"value": dense / t_or, "unit": "updates/s", "cores": cores, "kind": "oracle",

@@ -4,7 +4,8 @@
 // Sec. II) with the difference energy eps_n'(k + q) - eps_n(k) in the role of the band energy.
 //
 // Work decomposition, as the DOS forward: one workgroup per (tile of TX x TY x TZ cubes, band pair
-// (n, n')), one lane per cube looping over the six tetrahedra of Table I. The tile's grid points are
+// (n, n')), one lane per cube looping over the six tetrahedra of Table I; units tile-major, and each
+// XCD takes a contiguous range of them. The tile's grid points are
 // staged in LDS with eps_n at the point, eps_n' at the point shifted by q (periodic), and the product
 // weights W_m = b_mn(k) b_mn'(k + q). Per (tetrahedron, band pair) and occupation region, the
 // tetrahedron is clipped at eps = E_F and eps' = E_F into at most nine sub-tetrahedra (recomputed
@@ -77,8 +78,11 @@ __global__ __launch_bounds__(NT) void chi_kernel(ChiArgs a) {
   const int b = blockIdx.x;
   const int unit = (b % NXCD) * a.per_xcd + b / NXCD;
   if (unit >= a.nunits) return;
-  const int pair = unit / a.ntiles;
-  const int tile = unit - pair * a.ntiles;
+  // Tile-major units: the band pairs of one tile follow each other, so the tile's points (every band)
+  // stay in the XCD's L2 while its pairs run.
+  const int npairs = a.nb * a.nb;
+  const int tile = unit / npairs;
+  const int pair = unit - tile * npairs;
   const int n = pair / a.nb, np = pair - n * a.nb;
   const int TX = a.TX, TY = a.TY, TZ = a.TZ;
   const int PY = TY + 1, PZ = TZ + 1;
