@@ -153,15 +153,21 @@ def algorithmic_bytes(nk, nb, norb, ne):
     return fwd, bwd
 
 
-def load_traffic(kernel):
+def load_traffic(kernel, config=None):
+    """HBM bytes per launch of ``kernel`` from the committed counter summary, if it was profiled with
+    the current source and (where given) the same launch configuration; else None."""
     try:
         with open(TRAFFIC_FILE) as f:
-            rec = json.load(f).get(kernel)
+            recs = json.load(f).get(kernel)
     except (OSError, ValueError):
         return None
-    if not rec or rec.get("source_sha") != kernel_source_hash(kernel):
-        return None
-    return rec.get("bytes_per_launch")
+    for rec in recs if isinstance(recs, list) else [recs] if recs else []:
+        if rec.get("source_sha") != kernel_source_hash(kernel):
+            continue
+        if config is not None and rec.get("config") != config:
+            continue
+        return rec.get("bytes_per_launch")
+    return None
 
 
 def cpu_baseline(eps, w, grid, e0, de, ne, mode, G, gpu_fn):
@@ -211,8 +217,19 @@ def _read_csv(path):
         return list(csv.DictReader(f))
 
 
+def launch_configs(rec):
+    """Launch configuration per kernel of a bench record (what its traffic figures depend on)."""
+    cfg = rec.get("config", {})
+    out = {}
+    if "tile_forward" in cfg:
+        out["dos_forward_kernel"] = {"tile": cfg["tile_forward"]}
+    if "tile_backward" in cfg:
+        out["dos_backward_kernel"] = {"tile": cfg["tile_backward"]}
+    return out
+
+
 def summarize_profiles(kt_dir, fetch_dir=None, write_dir=None, copy_fetch_dir=None, copy_write_dir=None,
-                       command="", out_json=None, source_shas=None):
+                       command="", out_json=None, source_shas=None, configs=None):
     """Markdown summary of rocprofv3 output (kernel-trace stats, and HBM bytes from FETCH_SIZE /
     WRITE_SIZE scaled by what the same counters read for a device copy of known size)."""
     lines = ["| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
@@ -249,18 +266,21 @@ def summarize_profiles(kt_dir, fetch_dir=None, write_dir=None, copy_fetch_dir=No
                                ("chi_kernel", "chi_kernel")):
                 if pat in k:  # the kernels launched by one call add up (instantiations, gather pass)
                     sha = (source_shas or {}).get(short) or kernel_source_hash(short)
-                    rec = traffic.setdefault(short, {"source_sha": sha, "bytes_per_launch": 0.0,
-                                                     "read_bytes": 0.0, "write_bytes": 0.0})
+                    rec = traffic.setdefault(short, {"source_sha": sha, "config": (configs or {}).get(short),
+                                                     "bytes_per_launch": 0.0, "read_bytes": 0.0, "write_bytes": 0.0})
                     rec["bytes_per_launch"] += rd + wt
                     rec["read_bytes"] += rd
                     rec["write_bytes"] += wt
     if out_json and traffic:
-        try:  # keep the records of kernels this run did not profile
+        try:  # keep the records of kernels and launch configurations this run did not profile
             with open(out_json) as f:
                 merged = json.load(f)
         except (OSError, ValueError):
             merged = {}
-        merged.update(traffic)
+        for short, rec in traffic.items():
+            old = merged.get(short)
+            old = old if isinstance(old, list) else [old] if old else []
+            merged[short] = [r for r in old if r.get("config") != rec["config"]] + [rec]
         with open(out_json, "w") as f:
             json.dump(merged, f, indent=1)
     text = "\n".join(lines)
@@ -669,11 +689,14 @@ def main():
         ap.add_argument("--traffic-json")
         ap.add_argument("--bench-json", help="bench output of the profiled tree (its kernel source hashes)")
         a = ap.parse_args()
-        shas = None
+        shas = configs = None
         if a.bench_json:
             with open(a.bench_json) as f:
-                shas = json.loads(f.read().strip().splitlines()[-1]).get("kernel_source_sha")
-        summarize_profiles(a.kt, a.fetch, a.write, a.copy_fetch, a.copy_write, a.command, a.traffic_json, shas)
+                rec = json.loads(f.read().strip().splitlines()[-1])
+            shas = rec.get("kernel_source_sha")
+            configs = launch_configs(rec)
+        summarize_profiles(a.kt, a.fetch, a.write, a.copy_fetch, a.copy_write, a.command, a.traffic_json, shas,
+                           configs)
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -798,6 +821,8 @@ def main():
     else:
         kname, klabel, flops, t_k = "dos_forward_kernel", "dos_forward_kernel", f_fwd, t_fwd
     achieved = flops / t_k / 1e12
+    # the counter traffic depends on the launch configuration: reported only for the profiled one
+    traffic_cfg = {"tile": list(tetra.TILE_SHAPES[tile_b if kname == "dos_backward_kernel" else tile_f])}
     roofline = {
         "bound": "alu",
         "kernel": klabel,
@@ -805,7 +830,8 @@ def main():
         "peak": PEAK_FP32_VALU_TFLOPS,
         "unit": "TFLOP/s",
         "frac": achieved / PEAK_FP32_VALU_TFLOPS,
-        "traffic": load_traffic(kname),
+        "traffic": load_traffic(kname, traffic_cfg),
+        "traffic_config": traffic_cfg,
         "algorithmic_flops_per_launch": flops,
         "avg_launch_ms": t_k * 1e3,
     }
