@@ -257,28 +257,33 @@ __global__ __launch_bounds__(NT) void chi_kernel(ChiArgs a) {
           float e[4], ep[4];
           bool reg[2];
           if (!corners(t, c0, c1, pt, e, ep, reg)) continue;
-          float bb[4][NORB];
-#pragma unroll
-          for (int l = 0; l < 4; ++l)
-#pragma unroll
-            for (int m = 0; m < NORB; ++m) bb[l][m] = s_W[pt[l] * NORB + m];
 #pragma unroll 1
           for (int r = 0; r < 2; ++r) {
             if (!reg[r]) continue;
             const float sign = r == 0 ? 1.0f : -1.0f;
             unsigned long long* hreg = (PACKED && r == 1) ? hist_m : s_hist;
-            float f1c[4], f2c[4], P[4][4], f1[4];
-            region_planes(r, e, ep, ef, f1c, f2c);
+            // Occupation planes at the corners (f1, f2c <= 0 inside), the difference energies dd and
+            // the corners' points, reordered so that the corners inside the first plane come first:
+            // the first clipping then starts from the identity, whose unit rows fold into constants.
+            float f1[4], f2c[4], dd[4];
+            int q[4];
+            region_planes(r, e, ep, ef, f1, f2c);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              f1[i] = f1c[i];
-#pragma unroll
-              for (int c = 0; c < 4; ++c) P[i][c] = i == c ? 1.0f : 0.0f;
+            for (int c = 0; c < 4; ++c) {
+              dd[c] = ep[c] - e[c];
+              q[c] = pt[c];
             }
-            // The region is often the whole tetrahedron (n occupied and n' empty at every corner): the
-            // sort and the clipping are skipped there.
+            // The region is often the whole tetrahedron (n occupied and n' empty at every corner):
+            // the reordering and the first clipping are skipped there.
             const int ni1 = (f1[0] <= 0.0f) + (f1[1] <= 0.0f) + (f1[2] <= 0.0f) + (f1[3] <= 0.0f);
-            if (ni1 > 0 && ni1 < 4) inside_first(P, f1);
+            if (ni1 > 0 && ni1 < 4) inside_first_corners(f1, f2c, dd, q);
+            float bb[4][NORB];
+#pragma unroll
+            for (int l = 0; l < 4; ++l)
+#pragma unroll
+              for (int m = 0; m < NORB; ++m) bb[l][m] = s_W[q[l] * NORB + m];
+            constexpr float I[4][4] = {{1.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 1.0f, 0.0f, 0.0f},
+                                       {0.0f, 0.0f, 1.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 1.0f}};
 #pragma unroll 1
             for (int ia = 0; ia < clip_pieces(ni1); ++ia) {
               float A[4][4], f2[4];
@@ -286,9 +291,9 @@ __global__ __launch_bounds__(NT) void chi_kernel(ChiArgs a) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
 #pragma unroll
-                  for (int c = 0; c < 4; ++c) A[i][c] = P[i][c];
+                  for (int c = 0; c < 4; ++c) A[i][c] = I[i][c];
               } else {
-                clip_piece(P, f1, ni1, ia, A);
+                clip_piece(I, f1, ni1, ia, A);
               }
 #pragma unroll
               for (int i = 0; i < 4; ++i)
@@ -314,8 +319,8 @@ __global__ __launch_bounds__(NT) void chi_kernel(ChiArgs a) {
                 float d[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                  d[i] = __builtin_fmaf(S[i][0], ep[0] - e[0], __builtin_fmaf(S[i][1], ep[1] - e[1],
-                                        __builtin_fmaf(S[i][2], ep[2] - e[2], S[i][3] * (ep[3] - e[3]))));
+                  d[i] = __builtin_fmaf(S[i][0], dd[0], __builtin_fmaf(S[i][1], dd[1],
+                                        __builtin_fmaf(S[i][2], dd[2], S[i][3] * dd[3])));
                 int tag[4] = {0, 1, 2, 3};
                 bool sw[5];
                 sort4(d, tag, sw);
@@ -326,7 +331,6 @@ __global__ __launch_bounds__(NT) void chi_kernel(ChiArgs a) {
                 const TetSetup cs = tet_setup(d, a.e0, Vs);
                 tet_window(cs, a.de, c0, c1, jlo, jhi);
                 if (jlo > jhi) continue;
-                permute_rows(sw, S);
                 int jA, jB;
                 case_split(cs, a.de, a.inv_de, jlo, jhi, jA, jB);
                 float coef[4][4];
@@ -344,6 +348,8 @@ __global__ __launch_bounds__(NT) void chi_kernel(ChiArgs a) {
                     corner_dos_C(cs, local_y(cs, j, a.de), g);
                     g[3] = fmaxf(g[3], 0.0f);
                   }
+                  // the corner weights belong to the sorted vertices: back to the rows of S
+                  unsort4(sw, g);
                   float G[4];
                   parent_weights(S, g, G);
                   unsigned long long* h = &hreg[j - c0];

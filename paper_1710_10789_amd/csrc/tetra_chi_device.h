@@ -46,6 +46,31 @@ __host__ __device__ __forceinline__ int inside_first(float v[4][4], float f[4]) 
   return (f[0] <= 0.0f) + (f[1] <= 0.0f) + (f[2] <= 0.0f) + (f[3] <= 0.0f);
 }
 
+// The corners of a tetrahedron reordered (the same network) so that those with f <= 0 come first,
+// carrying two per-corner values x, y and the corner's point index q along. Relabelling the corners
+// of a tetrahedron changes nothing in its contribution, so the first clipping can then start from the
+// identity (unit barycentric rows) instead of a permuted one.
+__host__ __device__ __forceinline__ void inside_first_corners(float f[4], float x[4], float y[4], int q[4]) {
+  auto cx = [&](int a, int b) {
+    const bool sw = (f[a] > 0.0f) && !(f[b] > 0.0f);
+    const float fa = f[a], fb = f[b], xa = x[a], xb = x[b], ya = y[a], yb = y[b];
+    const int qa = q[a], qb = q[b];
+    f[a] = sw ? fb : fa;
+    f[b] = sw ? fa : fb;
+    x[a] = sw ? xb : xa;
+    x[b] = sw ? xa : xb;
+    y[a] = sw ? yb : ya;
+    y[b] = sw ? ya : yb;
+    q[a] = sw ? qb : qa;
+    q[b] = sw ? qa : qb;
+  };
+  cx(0, 1);
+  cx(2, 3);
+  cx(0, 2);
+  cx(1, 3);
+  cx(1, 2);
+}
+
 // Number of tetrahedra the part {f <= 0} splits into, for ni vertices inside.
 __host__ __device__ __forceinline__ int clip_pieces(int ni) { return ni == 0 ? 0 : (ni == 1 || ni == 4) ? 1 : 3; }
 
@@ -134,23 +159,20 @@ __host__ __device__ __forceinline__ bool region_possible(int r, float emin, floa
   return r == 0 ? (emin <= ef && epmax >= ef) : (emax >= ef && epmin <= ef);
 }
 
-// Rows of s reordered like the corners of a five-comparator sort4 with recorded exchanges sw
-// (so row l belongs to the l-th smallest difference energy).
-__host__ __device__ __forceinline__ void permute_rows(const bool sw[5], float s[4][4]) {
+// Values g[0..3] given in sorted-vertex order (after sort4 with recorded exchanges sw) put back into
+// the order of the vertices before the sort (the exchanges in reverse).
+__host__ __device__ __forceinline__ void unsort4(const bool sw[5], float g[4]) {
   constexpr int A[5] = {0, 2, 0, 1, 1}, B[5] = {1, 3, 2, 3, 2};
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const float x = s[A[k]][c], y = s[B[k]][c];
-      s[A[k]][c] = sw[k] ? y : x;
-      s[B[k]][c] = sw[k] ? x : y;
-    }
+  for (int k = 4; k >= 0; --k) {
+    const float a = g[A[k]], b = g[B[k]];
+    g[A[k]] = sw[k] ? b : a;
+    g[B[k]] = sw[k] ? a : b;
   }
 }
 
 // Parent-corner weights of one sub-tetrahedron at one energy: with g the corner weights dw/dE of its
-// sorted vertices (rows of s in sorted order), G_c = sum_l g_l s[l][c], so that sum_l g_l W(vertex l)
+// vertices (rows of s, g in the same order), G_c = sum_l g_l s[l][c], so that sum_l g_l W(vertex l)
 // = sum_c G_c W_c for W linear on the parent.
 __host__ __device__ __forceinline__ void parent_weights(const float s[4][4], const float g[4], float G[4]) {
 #pragma unroll

@@ -1,6 +1,7 @@
 // Host build of the susceptibility kernel's per-tetrahedron arithmetic (tetra_chi_device.h: the
-// occupation clipping into sub-tetrahedra, their volumes, the vertex reordering through the sort and
-// the parent-corner weights; tetra_device.h: the corner weights) against the FP64 oracle's
+// corner reordering and the occupation clipping into sub-tetrahedra, their volumes, the corner
+// weights put back from sorted-vertex order and the parent-corner weights; tetra_device.h: the corner
+// weights) against the FP64 oracle's
 // one-tetrahedron spectral weight. Test harness only: compiled by tests/test_chi_host.py with g++ and
 // linked with the oracle library.
 //
@@ -32,36 +33,53 @@ static float chi_fp32(const float e[4], const float ep[4], const float W[4], flo
   float total = 0.0f;
   for (int r = 0; r < 2; ++r) {
     if (!region_possible(r, emin, emax, epmin, epmax, ef)) continue;
-    float f1c[4], f2c[4];
-    region_planes(r, e, ep, ef, f1c, f2c);
-    float P[4][4], f1[4];
-    for (int i = 0; i < 4; ++i) {
-      f1[i] = f1c[i];
-      for (int c = 0; c < 4; ++c) P[i][c] = i == c ? 1.0f : 0.0f;
+    // as the kernel: corners reordered inside-first for the first plane, first clipping from the
+    // identity, the second from the first's pieces
+    float f1[4], f2c[4], dd[4];
+    int q[4];
+    region_planes(r, e, ep, ef, f1, f2c);
+    for (int c = 0; c < 4; ++c) {
+      dd[c] = ep[c] - e[c];
+      q[c] = c;
     }
-    const int ni1 = inside_first(P, f1);
+    const int ni1 = (f1[0] <= 0.0f) + (f1[1] <= 0.0f) + (f1[2] <= 0.0f) + (f1[3] <= 0.0f);
+    if (ni1 > 0 && ni1 < 4) inside_first_corners(f1, f2c, dd, q);
+    float Wq[4];
+    for (int c = 0; c < 4; ++c) Wq[c] = W[q[c]];
+    const float I[4][4] = {{1.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 1.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 1.0f, 0.0f},
+                           {0.0f, 0.0f, 0.0f, 1.0f}};
     for (int ia = 0; ia < clip_pieces(ni1); ++ia) {
       float A[4][4], f2[4];
-      clip_piece(P, f1, ni1, ia, A);
+      if (ni1 == 4) {
+        for (int i = 0; i < 4; ++i)
+          for (int c = 0; c < 4; ++c) A[i][c] = I[i][c];
+      } else {
+        clip_piece(I, f1, ni1, ia, A);
+      }
       for (int i = 0; i < 4; ++i) {
         f2[i] = 0.0f;
         for (int c = 0; c < 4; ++c) f2[i] = __builtin_fmaf(A[i][c], f2c[c], f2[i]);
       }
-      const int ni2 = inside_first(A, f2);
+      const int ni2 = (f2[0] <= 0.0f) + (f2[1] <= 0.0f) + (f2[2] <= 0.0f) + (f2[3] <= 0.0f);
+      if (ni2 > 0 && ni2 < 4) inside_first(A, f2);
       for (int ib = 0; ib < clip_pieces(ni2); ++ib) {
         float S[4][4];
-        clip_piece(A, f2, ni2, ib, S);
-        const float frac = sub_volume(S);
+        if (ni2 == 4) {
+          for (int i = 0; i < 4; ++i)
+            for (int c = 0; c < 4; ++c) S[i][c] = A[i][c];
+        } else {
+          clip_piece(A, f2, ni2, ib, S);
+        }
+        const float frac = (ni1 == 4 && ni2 == 4) ? 1.0f : sub_volume(S);
         if (!(frac > 0.0f)) continue;
         float d[4];
         for (int i = 0; i < 4; ++i) {
           d[i] = 0.0f;
-          for (int c = 0; c < 4; ++c) d[i] = __builtin_fmaf(S[i][c], ep[c] - e[c], d[i]);
+          for (int c = 0; c < 4; ++c) d[i] = __builtin_fmaf(S[i][c], dd[c], d[i]);
         }
         int tag[4] = {0, 1, 2, 3};
         bool sw[5];
         sort4(d, tag, sw);
-        permute_rows(sw, S);
         if (!(E > d[0] && E < d[3])) continue;
         const TetSetup cs = tet_setup(d, E, V * frac);  // local frames with e0 = E, j = 0
         float g[4];
@@ -74,9 +92,10 @@ static float chi_fp32(const float e[4], const float ep[4], const float W[4], flo
         } else {
           corner_dos_C(cs, local_y(cs, 0, 1.0f), g);
         }
+        unsort4(sw, g);
         float G[4];
         parent_weights(S, g, G);
-        const float v = G[0] * W[0] + G[1] * W[1] + G[2] * W[2] + G[3] * W[3];
+        const float v = G[0] * Wq[0] + G[1] * Wq[1] + G[2] * Wq[2] + G[3] * Wq[3];
         total += r == 0 ? v : -v;
       }
     }
