@@ -477,7 +477,7 @@ def bench_paper_shape(args, torch, tetra, dev):
     }), flush=True)
 
 
-def bench_nos(args, torch, tetra, dev):
+def nos_record(args, torch, tetra, dev, with_oracle=True):
     """Number of states and bin-averaged DOS at the headline shape (64^3 x 8 bands x 8 orbitals x 1000
     energies): one pass of each, inputs resident; tile shape by a short sweep outside the timed
     region. The FP64 oracle (dense in energy) is timed on the whole workload."""
@@ -543,7 +543,7 @@ def bench_nos(args, torch, tetra, dev):
         "tile_sweep_ms": sweep,
         "kernel_source_sha": {"nos_kernel": kernel_source_hash("nos_kernel")},
     }
-    if not args.no_cpu_baseline:
+    if with_oracle:
         import oracle
 
         oracle.build()
@@ -559,10 +559,14 @@ def bench_nos(args, torch, tetra, dev):
                                "sample": f"the whole workload, one number-of-states pass ({ne} energies), FP64 "
                                          f"({t_or:.1f} s)"}
         rec["nos_err_vs_oracle"] = float(np.abs(got - ref).max() / np.abs(ref).max())
-    print(json.dumps(rec), flush=True)
+    return rec
 
 
-def bench_chi(args, torch, tetra, dev):
+def bench_nos(args, torch, tetra, dev):
+    print(json.dumps(nos_record(args, torch, tetra, dev, with_oracle=not args.no_cpu_baseline)), flush=True)
+
+
+def chi_record(args, torch, tetra, dev, with_oracle=True):
     """Susceptibility spectral weight at the headline model: 64^3 grid, 8 bands x 8 orbitals, transfer
     q = (16, 16, 0) grid steps, 500 transfer energies from 0 to the band width, Fermi energy at half
     filling; every band pair. One JSON line (not the headline metric)."""
@@ -602,7 +606,7 @@ def bench_chi(args, torch, tetra, dev):
         "tile_ms": times,
         "kernel_source_sha": {"chi_kernel": kernel_source_hash("chi_kernel")},
     }
-    if not args.no_cpu_baseline:
+    if with_oracle:
         import oracle
 
         oracle.build()
@@ -621,10 +625,14 @@ def bench_chi(args, torch, tetra, dev):
         rec["error_vs_fp64_oracle"] = float(np.abs(got - ref).max() / np.abs(ref).max())
         rec["cpu_baseline"] = {"value": dense / t_or, "unit": "updates/s", "cores": cores, "kind": "oracle",
                                "sample": f"the whole workload, one pass, FP64 ({t_or:.1f} s)"}
-    print(json.dumps(rec), flush=True)
+    return rec
 
 
-def bench_batched(args, torch, tetra, dev):
+def bench_chi(args, torch, tetra, dev):
+    print(json.dumps(chi_record(args, torch, tetra, dev, with_oracle=not args.no_cpu_baseline)), flush=True)
+
+
+def batched_record(args, torch, tetra, dev):
     """32 independently seeded 8-orbital models, cubic grids from {24,32,48,64,96}^3 and 256..2048
     energies, through one persistent launch captured in a HIP graph, tile shapes per problem from the
     autotuner."""
@@ -657,7 +665,7 @@ def bench_batched(args, torch, tetra, dev):
                             args.steps, args.warmup)
     ms_single = _time_events(torch, lambda: [tetra.dos_forward(*p, tile=t) for p, t in zip(probs, tiles)],
                              args.steps, args.warmup)
-    print(json.dumps({
+    return {
         "metric": "tetra-band-energy updates/s, batched (32 models, one persistent graph-captured launch)",
         "value": dense / (ms_graph * 1e-3),
         "unit": "updates/s",
@@ -673,7 +681,11 @@ def bench_batched(args, torch, tetra, dev):
                    "dense_updates_per_pass": dense, "in_window_updates_per_pass": uwin,
                    "tiles": tiles, "host_eigh_s": t_gen},
         "ms": {"graph": ms_graph, "eager_batched": ms_eager, "one_launch_per_model": ms_single},
-    }), flush=True)
+    }
+
+
+def bench_batched(args, torch, tetra, dev):
+    print(json.dumps(batched_record(args, torch, tetra, dev)), flush=True)
 
 
 def main():
@@ -706,7 +718,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tiles", help="forward,backward tile shape ids (skips the autotuner)")
     ap.add_argument("--no-precision", action="store_true",
-                    help="headline run without the 128^3 x 16 x 16 x 2000 precision workload's extra keys")
+                    help="headline run without the extra keys of the other workloads (precision 128^3 x 16 x 16 "
+                         "x 2000, batched 32 models, number of states, susceptibility)")
     ap.add_argument("--workload", choices=["headline", "precision", "batched", "paper", "nos", "chi"], default="headline",
                     help="headline: 64^3 x 8 x 8 x 1000 fwd+bwd (the metric); precision: 128^3 x 16 x 16 x 2000 "
                          "with FP16 weights and exact accumulation; batched: 32 models, one persistent launch; "
@@ -912,6 +925,15 @@ def main():
         torch.cuda.empty_cache()
         out["precision_k128_b16_e2000"] = precision_measurement(args, torch, tetra, dev,
                                                                 with_oracle=not args.no_cpu_baseline)
+        torch.cuda.empty_cache()
+        # the other workloads' own lines, as extra keys (their values are not the headline value)
+        for key, fn in (("batched_batch32", lambda: batched_record(args, torch, tetra, dev)),
+                        ("nos_k64_b8_e1000", lambda: nos_record(args, torch, tetra, dev, with_oracle=False)),
+                        ("chi_k64_b8_w500", lambda: chi_record(args, torch, tetra, dev,
+                                                               with_oracle=not args.no_cpu_baseline))):
+            print(f"[bench] extra workload {key}", file=sys.stderr, flush=True)
+            out[key] = fn()
+            torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
 

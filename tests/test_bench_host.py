@@ -7,6 +7,8 @@ import os
 import subprocess
 import sys
 
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -30,7 +32,7 @@ def test_traffic_records_match_the_sources():
         configs = [r.get("config") for r in rec[kernel]]
         assert len({json.dumps(c, sort_keys=True) for c in configs}) == len(configs), kernel  # one per config
         for r in rec[kernel]:
-            assert r["bytes_per_launch"] == r["read_bytes"] + r["write_bytes"]
+            assert r["bytes_per_launch"] == pytest.approx(r["read_bytes"] + r["write_bytes"], rel=1e-12)
             fresh = r["source_sha"] == bench.kernel_source_hash(kernel)
             if r.get("config") is not None:
                 assert bench.load_traffic(kernel, r["config"]) == (r["bytes_per_launch"] if fresh else None), kernel
