@@ -15,7 +15,9 @@
  * and orbital weights b_mn(k) = |a^m_n(k)|^2 (eq. matrixelements) on the k-grid, stored as
  * linearised arrays (Sec. III.B), or the amplitudes a^m_n(k) themselves. Besides the DOS and its
  * adjoint: the orbital-resolved number of states with the integrated weights w_{n,l} (eq.
- * BZintegral) and the bin-averaged DOS derived from it.
+ * BZintegral), the bin-averaged DOS derived from it, and the orbital-resolved spectral weight of the
+ * bare susceptibility (its imaginary part at zero temperature; Sec. I and V name susceptibilities as
+ * the method's next use) by the same corner weights applied to the difference energy.
  *
  * Conventions shared by every entry point:
  *  - k-grid: n1 x n2 x n3 points, periodic, k = (i1*n2 + i2)*n3 + i3 (i3 fastest). Every grid point
