@@ -66,8 +66,14 @@ __device__ __forceinline__ float wave_sum_f(float v) {
   return v;
 }
 
+// Waves per SIMD the kernel is held to. Left alone, the compiler gives it 184-256 VGPRs (2 waves per
+// SIMD, or 1), and the clipping's long dependent chains then stall; held to 3 (4 with up to four
+// orbitals) it keeps some set-up values in scratch and runs 13-22 % faster (4, 8 and 16 orbitals
+// measured; 4 waves is slower from 8 orbitals on).
+constexpr int chi_waves(int norb) { return norb <= 4 ? 4 : 3; }
+
 template <int NORB, typename WT>
-__global__ __launch_bounds__(NT) void chi_kernel(ChiArgs a) {
+__global__ __launch_bounds__(NT, chi_waves(NORB)) void chi_kernel(ChiArgs a) {
   constexpr int RS = (HCAP / NORB - 1) | 1;  // histogram row stride (one row per orbital), odd
   __shared__ float s_e[NPMAX];
   __shared__ float s_ep[NPMAX];
