@@ -68,8 +68,9 @@ __device__ __forceinline__ float wave_sum_f(float v) {
 
 // Waves per SIMD the kernel is held to. Left alone, the compiler gives it 184-256 VGPRs (2 waves per
 // SIMD, or 1), and the clipping's long dependent chains then stall; held to 3 (4 with up to four
-// orbitals) it keeps some set-up values in scratch and runs 13-22 % faster (4, 8 and 16 orbitals
-// measured; 4 waves is slower from 8 orbitals on).
+// orbitals), with the corner data reloaded per region, it keeps at most a few set-up values in
+// scratch and runs 16-25 % faster (4, 8 and 16 orbitals measured; 4 waves is slower from 8 orbitals
+// on).
 constexpr int chi_waves(int norb) { return norb <= 4 ? 4 : 3; }
 
 template <int NORB, typename WT>
@@ -273,11 +274,22 @@ __global__ __launch_bounds__(NT, chi_waves(NORB)) void chi_kernel(ChiArgs a) {
             // the first clipping then starts from the identity, whose unit rows fold into constants.
             float f1[4], f2c[4], dd[4];
             int q[4];
-            region_planes(r, e, ep, ef, f1, f2c);
+            {
+              // the corners again from LDS (opaque indices: nothing of the tetrahedron stays live
+              // across the regions)
+              const uint32_t slots = tet_slots(t);
+              float er[4], epr[4];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-              dd[c] = ep[c] - e[c];
-              q[c] = pt[c];
+              for (int c = 0; c < 4; ++c) {
+                int pidx = pbase + point_offset((slots >> (4 * c)) & 7);
+                asm volatile("" : "+v"(pidx));
+                q[c] = pidx;
+                er[c] = s_e[pidx];
+                epr[c] = s_ep[pidx];
+              }
+              region_planes(r, er, epr, ef, f1, f2c);
+#pragma unroll
+              for (int c = 0; c < 4; ++c) dd[c] = epr[c] - er[c];
             }
             // The region is often the whole tetrahedron (n occupied and n' empty at every corner):
             // the reordering and the first clipping are skipped there.
