@@ -41,14 +41,15 @@ namespace {
 
 constexpr int NT = kTileCubes;      // one lane per cube of the tile
 constexpr int NPMAX = kTilePointsMax;  // staged grid points (cube corners) of the largest tile shape
-// LDS histogram capacity in 64-bit words. Up to 8 orbitals a workgroup then takes 25.6 KB of LDS, so
-// 6 workgroups (6 waves per SIMD) fit a CU; the kernel is held to that occupancy (80 VGPRs): 4 %
-// faster at the headline shape than 2048 words at 5 waves. Tile-band energy spans there stay within
-// 150 bins, one histogram pass.
+// LDS histogram capacity in 64-bit words, sized so that one more workgroup fits a CU, and the waves
+// per SIMD the kernel is held to. Up to 8 orbitals: 25.6 KB of LDS, 6 workgroups, 80 VGPRs (4 %
+// faster at 64^3 x 8 x 8 x 1000 than 2048 words at 5 waves; its tile-band energy spans stay within
+// 150 bins, one histogram pass). 16 orbitals: 39.7 KB, 4 workgroups, 128 VGPRs (10 % faster at
+// 128^3 x 16 x 16 x 2000 than 3 waves).
 template <int NORB>
-constexpr int fwd_hist_words() { return NORB <= 8 ? 1280 : 2048; }
+constexpr int fwd_hist_words() { return NORB <= 8 ? 1280 : NORB == 16 ? 1344 : 2048; }
 template <int NORB>
-constexpr int fwd_waves() { return NORB <= 8 ? 6 : 1; }
+constexpr int fwd_waves() { return NORB <= 8 ? 6 : NORB == 16 ? 4 : 1; }
 constexpr int NXCD = 8;
 
 struct FwdArgs {
