@@ -241,7 +241,6 @@ __device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
   frexpf(fminf(B, 3.0e38f), &bexp);  // B <= 2^bexp
   const int sexp = min((packed ? 30 : 62) - bexp, 126);
   const float S = ldexpf(1.0f, sexp);  // B * S <= 2^30 (packed) or 2^62
-  const double inv_S = ldexp(1.0, -sexp);
   // exact mode: shift from this workgroup's fixed point to the common one (negative: to the right)
   const int dshift = MODE == 2 ? exact_scale_exp(*a.gexp, a.lg_units) - sexp : 0;
   // Fold the power-of-two scale into the staged weights (exact): every deposit is then an integer-valued
@@ -253,6 +252,11 @@ __device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
     const int c1 = min(c0 + LC - 1, J1);
     const int L = c1 - c0 + 1;
     const int LW = L << cpl;  // words per row in this pass
+    // The lane index again, opaque: the addresses derived from it are formed in each pass instead of
+    // being kept live (in scratch) over the whole unit. (Not in the exact mode's second pass, whose
+    // register allocation it upsets.)
+    int tid = threadIdx.x;
+    if constexpr (MODE != 2) asm volatile("" : "+v"(tid));
     for (int q = tid; q < rows * LW; q += NT) {
       const int r = q / LW;
       s_hist[r * RS + (q - r * LW)] = 0ull;
@@ -362,7 +366,8 @@ __device__ __forceinline__ void forward_unit(const FwdArgs& a, int unit) {
           const unsigned long long w = hw[c];
           sum += packed ? (double)(unsigned)((m & 1) ? (w >> 32) : (w & 0xffffffffull)) : (double)(long long)w;
         }
-        if (sum != 0.0) atomic_add_global(&a.dos[(int64_t)(c0 + r) * NORB + m], (float)(sum * inv_S));
+        // the scale formed here rather than kept live over the passes (a register less there)
+        if (sum != 0.0) atomic_add_global(&a.dos[(int64_t)(c0 + r) * NORB + m], (float)ldexp(sum, -sexp));
       }
     }
     __syncthreads();
