@@ -863,6 +863,18 @@ def main():
                    "frac": (fwd_atomics / rate) / t_fwd,
                    "probe": f"{p_blocks} workgroups x 256 lanes x {4 * p_iters} conflict-free ds_add_u64"}
 
+    # the FP32 rate these kernels can issue: they are built without packed FP32, so their ceiling is
+    # that of independent non-packed FMAs (half the published figure), timed here with the probe
+    f_blocks, f_iters = cus * 32, 4096
+    ms_fma = _time_events(torch, lambda: probe.probe_fma_f32(f_blocks, f_iters, device=dev), 5, 2)
+    fma_tflops = f_blocks * 256 * f_iters * 16 * 2 / (ms_fma * 1e-3) / 1e12
+    fma_rate = {"tflops": fma_tflops, "frac_of_published": fma_tflops / PEAK_FP32_VALU_TFLOPS,
+                "forward_frac": f_fwd / t_fwd / 1e12 / fma_tflops,
+                "adjoint_frac": (f_bwd / t_bwd / 1e12 / fma_tflops) if use_bwd else None,
+                "probe": f"{f_blocks} workgroups x 256 lanes x {f_iters} x 16 independent v_fma_f32"}
+    roofline["attainable_tflops"] = fma_tflops
+    roofline["frac_attainable"] = achieved / fma_tflops
+
     out = {
         "metric": "tetra-band-energy updates/s at 64^3 k, 8 bands, 1000 E; fwd+bwd vs plain fwd",
         # dense-equivalent (tetrahedron, band, energy) triples of the workload per second of a step
@@ -903,6 +915,7 @@ def main():
         "roofline_bwd": ({"achieved": f_bwd / t_bwd / 1e12, "frac": f_bwd / t_bwd / 1e12 / PEAK_FP32_VALU_TFLOPS,
                           "hbm_gbs_algorithmic": b_bwd / t_bwd / 1e9} if use_bwd else None),
         "lds_atomic_ceiling": lds_ceiling,
+        "fp32_fma_rate": fma_rate,
         "kernel_source_sha": {k: kernel_source_hash(k) for k in KERNEL_SOURCES},
         "autotune_ms": {"forward": times_f, "backward": times_b},
         "fwd_worst_case_ms": worst_case_forward_ms(torch, tetra, eps_np, w_np, grid, e0, de, ne, tile_f),

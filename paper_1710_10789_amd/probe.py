@@ -1,8 +1,9 @@
-"""ctypes front end of ``libtetra_probe.so``, the benchmark's LDS-atomic measurement helper.
+"""ctypes front end of ``libtetra_probe.so``, the benchmark's measurement helpers.
 
 Not part of the DOS library: ``tetra_probe_lds_atomics`` times conflict-free 64-bit LDS atomic adds
 (the instruction of the kernels' histogram deposits), a ceiling the benchmark reports beside the
-forward kernel's time.
+forward kernel's time; ``tetra_probe_fma_f32`` times independent non-packed FP32 FMAs, the issue
+rate that bounds the kernels (all built without packed FP32 instructions).
 """
 from __future__ import annotations
 
@@ -21,6 +22,8 @@ def lib():
         L = ctypes.CDLL(_PATH)
         L.tetra_probe_lds_atomics.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
         L.tetra_probe_lds_atomics.restype = ctypes.c_int
+        L.tetra_probe_fma_f32.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+        L.tetra_probe_fma_f32.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -39,4 +42,22 @@ def probe_lds_atomics(blocks, iters, device=None, out=None):
                                        ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream))
     if st != 0:
         raise RuntimeError(f"tetra_probe_lds_atomics failed ({st})")
+    return out
+
+
+def probe_fma_f32(blocks, iters, device=None, out=None):
+    """Launch the FMA probe on the current stream (``blocks`` x 256 lanes x ``iters`` x 16 independent
+    FP32 FMAs); returns the float32 tensor ``[blocks * 256]`` of per-lane results."""
+    import torch
+
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    n = int(blocks) * 256
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=dev)
+    if out.dtype != torch.float32 or tuple(out.shape) != (n,) or out.device != dev:
+        raise ValueError("out must be a float32 tensor [blocks * 256] on the device")
+    st = lib().tetra_probe_fma_f32(int(blocks), int(iters), out.data_ptr(),
+                                   ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream))
+    if st != 0:
+        raise RuntimeError(f"tetra_probe_fma_f32 failed ({st})")
     return out

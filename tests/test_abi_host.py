@@ -43,9 +43,10 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_measurement_probe_is_not_in_the_product_library(L):
-    """The LDS-atomic probe is a benchmark helper of its own library, not part of the C ABI."""
+    """The LDS-atomic and FMA probes are benchmark helpers of their own library, not part of the C ABI."""
     assert "tetra_probe" not in open(HEADER).read()
     assert not hasattr(L, "tetra_probe_lds_atomics")
+    assert not hasattr(L, "tetra_probe_fma_f32")
 
 
 def test_status_strings(L):
@@ -278,6 +279,10 @@ def test_probe_rejects_bad_arguments():
     assert P.tetra_probe_lds_atomics(4, 0, FAKE, None) == -1
     assert P.tetra_probe_lds_atomics(4, 10, None, None) == -1
     assert P.tetra_probe_lds_atomics((1 << 24) + 1, 10, FAKE, None) == -1
+    assert P.tetra_probe_fma_f32(0, 10, FAKE, None) == -1
+    assert P.tetra_probe_fma_f32(4, 0, FAKE, None) == -1
+    assert P.tetra_probe_fma_f32(4, 10, None, None) == -1
+    assert P.tetra_probe_fma_f32(4, (1 << 24) + 1, FAKE, None) == -1
 
 
 def test_backward_workspace_sizes(L):
