@@ -4,20 +4,25 @@
 // Sec. II) with the difference energy eps_n'(k + q) - eps_n(k) in the role of the band energy.
 //
 // Work decomposition, as the DOS forward: one workgroup per (tile of TX x TY x TZ cubes, band pair
-// (n, n')), one lane per cube looping over the six tetrahedra of Table I; units tile-major, and each
-// XCD takes a contiguous range of them. The tile's grid points are
-// staged in LDS with eps_n at the point, eps_n' at the point shifted by q (periodic), and the product
-// weights W_m = b_mn(k) b_mn'(k + q). Per (tetrahedron, band pair) and occupation region, the
-// tetrahedron is clipped at eps = E_F and eps' = E_F into at most nine sub-tetrahedra (recomputed
-// piece by piece, nothing stored); each takes the DOS treatment of the forward kernel (sort, exact
-// window, case split, corner weights of Sec. II.C), its corner weights are mapped back to the parent's
-// corners through its barycentric coordinates and contracted with the corner weights W. The LDS
-// histograms hold fixed point with a power-of-two scale from a bound: the part of a tetrahedron on
-// either side of an occupation boundary has a section no larger than the whole tetrahedron's, so a
-// tetrahedron adds at most 12 V max|W| / (max - min of eps' - eps) to any bin (V = V_T/(4 V_G)). With
-// non-negative weights each region's terms are non-negative: one histogram per region, two orbitals
-// per 64-bit word; otherwise one signed 64-bit histogram. One global float atomic per touched
-// (energy, orbital) bin at the end.
+// (n, n')), units tile-major, and each XCD takes a contiguous range of them. The tile's grid points
+// are staged in LDS with eps_n at the point, eps_n' at the point shifted by q (periodic), and the
+// product weights W_m = b_mn(k) b_mn'(k + q). Each energy pass runs two sweeps:
+//  * one lane per cube over the six tetrahedra of Table I: an occupation region that is the whole
+//    tetrahedron (band n occupied and n' empty at every corner, or the reverse; most of them) is the
+//    DOS of eps' - eps formed as in the forward kernel (sort, exact window, case split, corner weights
+//    of Sec. II.C); the other regions that may be non-empty go to a queue in LDS;
+//  * every lane over the queued regions' sub-tetrahedra: a region is clipped at eps = E_F and
+//    eps' = E_F into at most nine of them (held as barycentric rows in the parent); each takes the
+//    same DOS treatment with W formed at its vertices and its share of the volume. The regions that
+//    need clipping lie where a band crosses E_F, in a few cubes of a tile: shared out piece by piece
+//    they no longer hold one wavefront, and the workgroup behind its barrier, for the whole pass.
+// The LDS histograms hold fixed point with a power-of-two scale from a bound: the part of a
+// tetrahedron on either side of an occupation boundary has a section no larger than the whole
+// tetrahedron's, so a tetrahedron adds at most 12 V max|W| / (max - min of eps' - eps) to any bin
+// (V = V_T/(4 V_G)). With non-negative weights each region's terms are non-negative: one histogram per
+// region, two orbitals per 64-bit word; otherwise one signed 64-bit histogram. The sums are exact
+// integers, so the order in which the queue is filled and worked off does not change them. One global
+// float atomic per touched (energy, orbital) bin at the end.
 
 #include <type_traits>
 
@@ -66,12 +71,10 @@ __device__ __forceinline__ float wave_sum_f(float v) {
   return v;
 }
 
-// Waves per SIMD the kernel is held to. Left alone, the compiler gives it 184-256 VGPRs (2 waves per
-// SIMD, or 1), and the clipping's long dependent chains then stall; held to 3 (4 with up to four
-// orbitals), with the corner data reloaded per region, it keeps at most a few set-up values in
-// scratch and runs 16-25 % faster (4, 8 and 16 orbitals measured; 4 waves is slower from 8 orbitals
-// on).
-constexpr int chi_waves(int norb) { return norb <= 4 ? 4 : 3; }
+// Waves per SIMD the kernel is held to. With nothing of the clipping live over a sub-tetrahedron's
+// energy loop it needs 100-140 VGPRs up to 8 orbitals (139 at 8: held to 4 waves it keeps 8 values in
+// scratch, 2.00 against 2.27 ms at 3 waves for the 64^3 x 8 x 8 x 500 workload) and up to 196 at 16.
+constexpr int chi_waves(int norb) { return norb <= 8 ? 4 : 3; }
 
 template <int NORB, typename WT>
 __global__ __launch_bounds__(NT, chi_waves(NORB)) void chi_kernel(ChiArgs a) {
@@ -81,6 +84,10 @@ __global__ __launch_bounds__(NT, chi_waves(NORB)) void chi_kernel(ChiArgs a) {
   __shared__ float s_W[NPMAX * NORB];
   __shared__ unsigned long long s_hist[HCAP];
   __shared__ float s_red[8 * (NT / 64)];
+  // regions to clip, queued by the first sweep of a pass and shared out over every lane by the second:
+  // lane of the cube << 4 | tetrahedron << 1 | region (at most 6 x 2 per cube)
+  __shared__ unsigned short s_q[NT * 12];
+  __shared__ int s_qn;
 
   const int b = blockIdx.x;
   const int unit = (b % NXCD) * a.per_xcd + b / NXCD;
@@ -167,7 +174,9 @@ __global__ __launch_bounds__(NT, chi_waves(NORB)) void chi_kernel(ChiArgs a) {
   auto point_offset = [PY, PZ](int s) { return (s & 1) * (PY * PZ) + ((s >> 1) & 1) * PZ + (s >> 2); };
 
   // Corner data of tetrahedron t of this lane's cube; false when it cannot contribute to [lo, hi].
-  auto corners = [&](int t, int lo, int hi, int pt[4], float e[4], float ep[4], bool reg[2]) {
+  // whole: the region that is the whole tetrahedron (n occupied and n' empty at every corner for region
+  // 0, the reverse for region 1), or -1.
+  auto corners = [&](int t, int lo, int hi, int pt[4], float e[4], float ep[4], bool reg[2], int& whole) {
     const uint32_t slots = tet_slots(t);
     float emin = __builtin_huge_valf(), emax = -emin, pmin = emin, pmax = -emin, dmin = emin, dmax = -emin;
     bool fin = true;
@@ -185,6 +194,7 @@ __global__ __launch_bounds__(NT, chi_waves(NORB)) void chi_kernel(ChiArgs a) {
       dmax = fmaxf(dmax, ep[l] - e[l]);
     }
     if (!fin || !(dmax > dmin)) return false;
+    whole = (emax <= ef && pmin >= ef) ? 0 : (emin >= ef && pmax <= ef) ? 1 : -1;
     reg[0] = region_possible(0, emin, emax, pmin, pmax, ef);
     reg[1] = region_possible(1, emin, emax, pmin, pmax, ef);
     if (!reg[0] && !reg[1]) return false;
@@ -202,7 +212,8 @@ __global__ __launch_bounds__(NT, chi_waves(NORB)) void chi_kernel(ChiArgs a) {
       int pt[4];
       float e[4], ep[4];
       bool reg[2];
-      if (!corners(t, J0, J1, pt, e, ep, reg)) continue;
+      int whole;
+      if (!corners(t, J0, J1, pt, e, ep, reg, whole)) continue;
       float dmin = ep[0] - e[0], dmax = dmin;
 #pragma unroll
       for (int l = 1; l < 4; ++l) {
@@ -247,6 +258,48 @@ __global__ __launch_bounds__(NT, chi_waves(NORB)) void chi_kernel(ChiArgs a) {
     constexpr int RSP = (HCAP / 2 / NPAIR - 1) | 1;
     constexpr int RSX = PACKED ? RSP : RS;
     unsigned long long* hist_m = s_hist + (PACKED ? HCAP / 2 : 0);  // region -1 (packed only)
+    // Corner weights dw/dE of a (sub-)tetrahedron's sorted vertices at grid energy j.
+    auto corner_g = [&](const TetSetup& cs, const float (&coef)[4][4], int j, int jA, int jB, float g[4]) {
+      if (j <= jA) {
+        corner_dos_A(cs, local_x(cs, j, a.de), g);
+        g[0] = fmaxf(g[0], 0.0f);
+      } else if (j <= jB) {
+        corner_dos_B_poly(coef, local_z(cs, j, a.de), g);
+#pragma unroll
+        for (int l = 0; l < 4; ++l) g[l] = fmaxf(g[l], 0.0f);
+      } else {
+        corner_dos_C(cs, local_y(cs, j, a.de), g);
+        g[3] = fmaxf(g[3], 0.0f);
+      }
+    };
+    // One energy's terms sum_l G_l Wr[l][m] into the region's histogram row h.
+    auto deposit = [&](unsigned long long* h, float G[4], const float (&Wr)[4][NORB], float sign) {
+      if (PACKED) {
+        // non-negative terms: the truncating conversion of 1/2 + v rounds (halves up)
+#pragma unroll
+        for (int pr = 0; pr < NPAIR; ++pr) {
+          const int m0 = 2 * pr, m1 = 2 * pr + 1;
+          const float v0 = __builtin_fmaf(G[0], Wr[0][m0], __builtin_fmaf(G[1], Wr[1][m0],
+                           __builtin_fmaf(G[2], Wr[2][m0], __builtin_fmaf(G[3], Wr[3][m0], 0.5f))));
+          unsigned long long word = (unsigned long long)(unsigned)v0;
+          if (m1 < NORB) {
+            const float v1 = __builtin_fmaf(G[0], Wr[0][m1], __builtin_fmaf(G[1], Wr[1][m1],
+                             __builtin_fmaf(G[2], Wr[2][m1], __builtin_fmaf(G[3], Wr[3][m1], 0.5f))));
+            word |= (unsigned long long)(unsigned)v1 << 32;
+          }
+          atomicAdd(&h[pr * RSX], word);
+        }
+      } else {
+#pragma unroll
+        for (int l = 0; l < 4; ++l) G[l] *= sign;
+#pragma unroll
+        for (int m = 0; m < NORB; ++m) {
+          const float v = __builtin_fmaf(G[0], Wr[0][m], __builtin_fmaf(G[1], Wr[1][m],
+                                         __builtin_fmaf(G[2], Wr[2][m], G[3] * Wr[3][m])));
+          atomicAdd(&h[m * RSX], (unsigned long long)__float2ll_rn(v));
+        }
+      }
+    };
     for (int c0 = J0; c0 <= J1; c0 += RSX) {
       const int c1 = min(c0 + RSX - 1, J1);
       const int L = c1 - c0 + 1;
@@ -256,150 +309,158 @@ __global__ __launch_bounds__(NT, chi_waves(NORB)) void chi_kernel(ChiArgs a) {
         s_hist[m * RSX + (q - m * L)] = 0ull;
         if (PACKED) hist_m[m * RSX + (q - m * L)] = 0ull;
       }
+      if (tid == 0) s_qn = 0;
       __syncthreads();
+      // First sweep, every lane on its own cube: the regions that are the whole tetrahedron, most of
+      // them, as the forward kernel forms a DOS (the corners sorted with their points, the weights read
+      // in sorted order: no clipping, no parent-corner weights, nothing to put back per energy), and
+      // the other regions queued. The regions that need clipping lie where a band crosses E_F, in a
+      // few cubes of the tile; sharing them out over all lanes keeps them from holding one wavefront,
+      // and the workgroup behind its barrier, for the whole pass.
       if (valid) {
 #pragma unroll 1
         for (int t = 0; t < 6; ++t) {
           int pt[4];
           float e[4], ep[4];
           bool reg[2];
-          if (!corners(t, c0, c1, pt, e, ep, reg)) continue;
-#pragma unroll 1
-          for (int r = 0; r < 2; ++r) {
-            if (!reg[r]) continue;
-            const float sign = r == 0 ? 1.0f : -1.0f;
-            unsigned long long* hreg = (PACKED && r == 1) ? hist_m : s_hist;
-            // Occupation planes at the corners (f1, f2c <= 0 inside), the difference energies dd and
-            // the corners' points, reordered so that the corners inside the first plane come first:
-            // the first clipping then starts from the identity, whose unit rows fold into constants.
-            float f1[4], f2c[4], dd[4];
-            int q[4];
-            {
-              // the corners again from LDS (opaque indices: nothing of the tetrahedron stays live
-              // across the regions)
-              const uint32_t slots = tet_slots(t);
-              float er[4], epr[4];
+          int whole;
+          if (!corners(t, c0, c1, pt, e, ep, reg, whole)) continue;
 #pragma unroll
-              for (int c = 0; c < 4; ++c) {
-                int pidx = pbase + point_offset((slots >> (4 * c)) & 7);
-                asm volatile("" : "+v"(pidx));
-                q[c] = pidx;
-                er[c] = s_e[pidx];
-                epr[c] = s_ep[pidx];
-              }
-              region_planes(r, er, epr, ef, f1, f2c);
+          for (int r = 0; r < 2; ++r)
+            if (reg[r] && r != whole) s_q[atomicAdd(&s_qn, 1)] = (unsigned short)((tid << 4) | (t << 1) | r);
+          if (whole < 0) continue;
+          float d[4];
 #pragma unroll
-              for (int c = 0; c < 4; ++c) dd[c] = epr[c] - er[c];
-            }
-            // The region is often the whole tetrahedron (n occupied and n' empty at every corner):
-            // the reordering and the first clipping are skipped there.
-            const int ni1 = (f1[0] <= 0.0f) + (f1[1] <= 0.0f) + (f1[2] <= 0.0f) + (f1[3] <= 0.0f);
-            if (ni1 > 0 && ni1 < 4) inside_first_corners(f1, f2c, dd, q);
-            float bb[4][NORB];
+          for (int c = 0; c < 4; ++c) d[c] = ep[c] - e[c];
+          sort4(d, pt);
+          int jlo, jhi;
+          energy_window(d[0], d[3], a.e0, a.inv_de, c0, c1, jlo, jhi);
+          if (jlo > jhi + 2) continue;
+          const TetSetup cs = tet_setup(d, a.e0, VS);
+          tet_window(cs, a.de, c0, c1, jlo, jhi);
+          if (jlo > jhi) continue;
+          float ws[4][NORB];
 #pragma unroll
-            for (int l = 0; l < 4; ++l)
+          for (int l = 0; l < 4; ++l)
 #pragma unroll
-              for (int m = 0; m < NORB; ++m) bb[l][m] = s_W[q[l] * NORB + m];
-            constexpr float I[4][4] = {{1.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 1.0f, 0.0f, 0.0f},
-                                       {0.0f, 0.0f, 1.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 1.0f}};
-#pragma unroll 1
-            for (int ia = 0; ia < clip_pieces(ni1); ++ia) {
-              float A[4][4], f2[4];
-              if (ni1 == 4) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                  for (int c = 0; c < 4; ++c) A[i][c] = I[i][c];
-              } else {
-                clip_piece(I, f1, ni1, ia, A);
-              }
-#pragma unroll
-              for (int i = 0; i < 4; ++i)
-                f2[i] = __builtin_fmaf(A[i][0], f2c[0], __builtin_fmaf(A[i][1], f2c[1],
-                                       __builtin_fmaf(A[i][2], f2c[2], A[i][3] * f2c[3])));
-              const int ni2 = (f2[0] <= 0.0f) + (f2[1] <= 0.0f) + (f2[2] <= 0.0f) + (f2[3] <= 0.0f);
-              if (ni2 > 0 && ni2 < 4) inside_first(A, f2);
-#pragma unroll 1
-              for (int ib = 0; ib < clip_pieces(ni2); ++ib) {
-                float S[4][4];
-                float frac;
-                if (ni2 == 4) {
-#pragma unroll
-                  for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) S[i][c] = A[i][c];
-                  frac = ni1 == 4 ? 1.0f : sub_volume(S);
-                } else {
-                  clip_piece(A, f2, ni2, ib, S);
-                  frac = sub_volume(S);
-                }
-                if (!(frac > 0.0f)) continue;
-                float d[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                  d[i] = __builtin_fmaf(S[i][0], dd[0], __builtin_fmaf(S[i][1], dd[1],
-                                        __builtin_fmaf(S[i][2], dd[2], S[i][3] * dd[3])));
-                int tag[4] = {0, 1, 2, 3};
-                bool sw[5];
-                sort4(d, tag, sw);
-                int jlo, jhi;
-                energy_window(d[0], d[3], a.e0, a.inv_de, c0, c1, jlo, jhi);
-                if (jlo > jhi + 2) continue;
-                const float Vs = VS * frac;
-                const TetSetup cs = tet_setup(d, a.e0, Vs);
-                tet_window(cs, a.de, c0, c1, jlo, jhi);
-                if (jlo > jhi) continue;
-                int jA, jB;
-                case_split(cs, a.de, a.inv_de, jlo, jhi, jA, jB);
-                float coef[4][4];
-                if (jB > jA) corner_dos_B_coeffs(cs, Vs, coef);
-                for (int j = jlo; j <= jhi; ++j) {
-                  float g[4];
-                  if (j <= jA) {
-                    corner_dos_A(cs, local_x(cs, j, a.de), g);
-                    g[0] = fmaxf(g[0], 0.0f);
-                  } else if (j <= jB) {
-                    corner_dos_B_poly(coef, local_z(cs, j, a.de), g);
-#pragma unroll
-                    for (int l = 0; l < 4; ++l) g[l] = fmaxf(g[l], 0.0f);
-                  } else {
-                    corner_dos_C(cs, local_y(cs, j, a.de), g);
-                    g[3] = fmaxf(g[3], 0.0f);
-                  }
-                  // the corner weights belong to the sorted vertices: back to the rows of S
-                  unsort4(sw, g);
-                  float G[4];
-                  parent_weights(S, g, G);
-                  unsigned long long* h = &hreg[j - c0];
-                  if (PACKED) {
-                    // non-negative terms: the truncating conversion of 1/2 + v rounds (halves up)
-#pragma unroll
-                    for (int pr = 0; pr < NPAIR; ++pr) {
-                      const int m0 = 2 * pr, m1 = 2 * pr + 1;
-                      const float v0 = __builtin_fmaf(G[0], bb[0][m0], __builtin_fmaf(G[1], bb[1][m0],
-                                       __builtin_fmaf(G[2], bb[2][m0], __builtin_fmaf(G[3], bb[3][m0], 0.5f))));
-                      unsigned long long word = (unsigned long long)(unsigned)v0;
-                      if (m1 < NORB) {
-                        const float v1 = __builtin_fmaf(G[0], bb[0][m1], __builtin_fmaf(G[1], bb[1][m1],
-                                         __builtin_fmaf(G[2], bb[2][m1], __builtin_fmaf(G[3], bb[3][m1], 0.5f))));
-                        word |= (unsigned long long)(unsigned)v1 << 32;
-                      }
-                      atomicAdd(&h[pr * RSX], word);
-                    }
-                  } else {
-#pragma unroll
-                    for (int l = 0; l < 4; ++l) G[l] *= sign;
-#pragma unroll
-                    for (int m = 0; m < NORB; ++m) {
-                      const float v = __builtin_fmaf(G[0], bb[0][m], __builtin_fmaf(G[1], bb[1][m],
-                                                     __builtin_fmaf(G[2], bb[2][m], G[3] * bb[3][m])));
-                      atomicAdd(&h[m * RSX], (unsigned long long)__float2ll_rn(v));
-                    }
-                  }
-                }
-              }
-            }
+            for (int m = 0; m < NORB; ++m) ws[l][m] = s_W[pt[l] * NORB + m];
+          int jA, jB;
+          case_split(cs, a.de, a.inv_de, jlo, jhi, jA, jB);
+          float coef[4][4];
+          if (jB > jA) corner_dos_B_coeffs(cs, VS, coef);
+          const float sign = whole == 0 ? 1.0f : -1.0f;
+          unsigned long long* hreg = (PACKED && whole == 1) ? hist_m : s_hist;
+          for (int j = jlo; j <= jhi; ++j) {
+            float g[4];
+            corner_g(cs, coef, j, jA, jB, g);
+            deposit(&hreg[j - c0], g, ws, sign);
           }
+        }
+      }
+      __syncthreads();
+      // Second sweep: the queued regions, clipped at the two occupation boundaries into at most 3 x 3
+      // sub-tetrahedra. The lanes take (region, first piece, second piece) slots, so the pieces are
+      // shared out evenly; each slot redoes its region's planes and first clipping from LDS (nothing
+      // of the clipping stays live over a piece's energy loop) and leaves early if its piece does
+      // not exist.
+      const int nq = s_qn;
+      constexpr float I[4][4] = {{1.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 1.0f, 0.0f, 0.0f},
+                                 {0.0f, 0.0f, 1.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 1.0f}};
+#pragma unroll 1
+      for (int ip = tid; ip < 9 * nq; ip += NT) {
+        const int iq = ip / 9, piece = ip - 9 * iq;
+        const int ia = piece / 3, ib = piece - 3 * ia;
+        const int item = s_q[iq];
+        const int it = item >> 4, t = (item >> 1) & 7, r = item & 1;
+        const int qz = it % TZ, qy = (it / TZ) % TY, qx = it / (TZ * TY);
+        const int qbase = (qx * PY + qy) * PZ + qz;
+        // Occupation planes at the corners (f1, f2c <= 0 inside), the difference energies dd and the
+        // corners' points, reordered so that the corners inside the first plane come first: the first
+        // clipping then starts from the identity, whose unit rows fold into constants.
+        float f1[4], f2c[4], dd[4];
+        int q[4];
+        {
+          const uint32_t slots = tet_slots(t);
+          float er[4], epr[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            q[c] = qbase + point_offset((slots >> (4 * c)) & 7);
+            er[c] = s_e[q[c]];
+            epr[c] = s_ep[q[c]];
+          }
+          region_planes(r, er, epr, ef, f1, f2c);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) dd[c] = epr[c] - er[c];
+        }
+        const int ni1 = (f1[0] <= 0.0f) + (f1[1] <= 0.0f) + (f1[2] <= 0.0f) + (f1[3] <= 0.0f);
+        if (ia >= clip_pieces(ni1)) continue;
+        if (ni1 > 0 && ni1 < 4) inside_first_corners(f1, f2c, dd, q);
+        float A[4][4], f2[4];
+        if (ni1 == 4) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) A[i][c] = I[i][c];
+        } else {
+          clip_piece(I, f1, ni1, ia, A);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          f2[i] = __builtin_fmaf(A[i][0], f2c[0], __builtin_fmaf(A[i][1], f2c[1],
+                                 __builtin_fmaf(A[i][2], f2c[2], A[i][3] * f2c[3])));
+        const int ni2 = (f2[0] <= 0.0f) + (f2[1] <= 0.0f) + (f2[2] <= 0.0f) + (f2[3] <= 0.0f);
+        if (ib >= clip_pieces(ni2)) continue;
+        if (ni2 > 0 && ni2 < 4) inside_first(A, f2);
+        float S[4][4];
+        float frac;
+        if (ni2 == 4) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) S[i][c] = A[i][c];
+          frac = ni1 == 4 ? 1.0f : sub_volume(S);
+        } else {
+          clip_piece(A, f2, ni2, ib, S);
+          frac = sub_volume(S);
+        }
+        if (!(frac > 0.0f)) continue;
+        float d[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          d[i] = __builtin_fmaf(S[i][0], dd[0], __builtin_fmaf(S[i][1], dd[1],
+                                __builtin_fmaf(S[i][2], dd[2], S[i][3] * dd[3])));
+        sort4_rows(d, S);
+        int jlo, jhi;
+        energy_window(d[0], d[3], a.e0, a.inv_de, c0, c1, jlo, jhi);
+        if (jlo > jhi + 2) continue;
+        const float Vs = VS * frac;
+        const TetSetup cs = tet_setup(d, a.e0, Vs);
+        tet_window(cs, a.de, c0, c1, jlo, jhi);
+        if (jlo > jhi) continue;
+        // W at the sorted vertices (linear on the parent): Wv[l] = sum_c S[l][c] W_c
+        float wv[4][NORB];
+#pragma unroll
+        for (int l = 0; l < 4; ++l)
+#pragma unroll
+          for (int m = 0; m < NORB; ++m) wv[l][m] = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+          for (int m = 0; m < NORB; ++m) {
+            const float wc = s_W[q[c] * NORB + m];
+#pragma unroll
+            for (int l = 0; l < 4; ++l) wv[l][m] = __builtin_fmaf(S[l][c], wc, wv[l][m]);
+          }
+        int jA, jB;
+        case_split(cs, a.de, a.inv_de, jlo, jhi, jA, jB);
+        float coef[4][4];
+        if (jB > jA) corner_dos_B_coeffs(cs, Vs, coef);
+        const float sign = r == 0 ? 1.0f : -1.0f;
+        unsigned long long* hreg = (PACKED && r == 1) ? hist_m : s_hist;
+        for (int j = jlo; j <= jhi; ++j) {
+          float g[4];
+          corner_g(cs, coef, j, jA, jB, g);
+          deposit(&hreg[j - c0], g, wv, sign);
         }
       }
       __syncthreads();

@@ -159,25 +159,27 @@ __host__ __device__ __forceinline__ bool region_possible(int r, float emin, floa
   return r == 0 ? (emin <= ef && epmax >= ef) : (emax >= ef && epmin <= ef);
 }
 
-// Values g[0..3] given in sorted-vertex order (after sort4 with recorded exchanges sw) put back into
-// the order of the vertices before the sort (the exchanges in reverse).
-__host__ __device__ __forceinline__ void unsort4(const bool sw[5], float g[4]) {
-  constexpr int A[5] = {0, 2, 0, 1, 1}, B[5] = {1, 3, 2, 3, 2};
+// Vertices of a sub-tetrahedron (rows of s, barycentric in the parent) sorted with their values d into
+// ascending d, by the five-comparator network of sort4 (equal values may end in either order; the
+// contribution does not depend on it).
+__host__ __device__ __forceinline__ void sort4_rows(float d[4], float s[4][4]) {
+  auto cx = [&](int a, int b) {
+    const bool sw = d[b] < d[a];
+    const float lo = sw ? d[b] : d[a], hi = sw ? d[a] : d[b];
+    d[a] = lo;
+    d[b] = hi;
 #pragma unroll
-  for (int k = 4; k >= 0; --k) {
-    const float a = g[A[k]], b = g[B[k]];
-    g[A[k]] = sw[k] ? b : a;
-    g[B[k]] = sw[k] ? a : b;
-  }
-}
-
-// Parent-corner weights of one sub-tetrahedron at one energy: with g the corner weights dw/dE of its
-// vertices (rows of s, g in the same order), G_c = sum_l g_l s[l][c], so that sum_l g_l W(vertex l)
-// = sum_c G_c W_c for W linear on the parent.
-__host__ __device__ __forceinline__ void parent_weights(const float s[4][4], const float g[4], float G[4]) {
-#pragma unroll
-  for (int c = 0; c < 4; ++c)
-    G[c] = __builtin_fmaf(g[0], s[0][c], __builtin_fmaf(g[1], s[1][c], __builtin_fmaf(g[2], s[2][c], g[3] * s[3][c])));
+    for (int c = 0; c < 4; ++c) {
+      const float x = s[a][c], y = s[b][c];
+      s[a][c] = sw ? y : x;
+      s[b][c] = sw ? x : y;
+    }
+  };
+  cx(0, 1);
+  cx(2, 3);
+  cx(0, 2);
+  cx(1, 3);
+  cx(1, 2);
 }
 
 }  // namespace tetra

@@ -1,8 +1,9 @@
 """The susceptibility kernel's per-tetrahedron arithmetic (``tetra_chi_device.h``: clipping at the two
-occupation boundaries into sub-tetrahedra, their volumes, vertex reordering and parent-corner weights,
-with the corner weights of ``tetra_device.h``) built for the host with g++ and checked against the
-FP64 oracle's one-tetrahedron spectral weight on random tetrahedra, generic and with nearly equal
-corners. No GPU needed; the harness is test code only.
+occupation boundaries into sub-tetrahedra, their volumes, their vertices sorted with their barycentric
+rows and the weights formed at them, with the corner weights of ``tetra_device.h``) built for the host
+with g++ and checked against the FP64 oracle's one-tetrahedron spectral weight on random tetrahedra,
+generic, with nearly equal corners, and with a region that is the whole tetrahedron (the kernel's
+unclipped path). No GPU needed; the harness is test code only.
 
 Bound: |S_fp32 - S_oracle| <= 1e-4 of vol * max W / (max - min of eps' - eps), the size of one
 tetrahedron's contribution (a wrong piece, sign or vertex order gives O(1))."""
@@ -30,6 +31,6 @@ def test_chi_clipping_against_oracle(tmp_path, oracle_lib):
     assert res.returncode == 0, res.stderr
     parts = res.stdout.split()
     print(res.stdout)
-    cases, nonzero, worst = int(parts[1]), int(parts[2]), float(parts[3])
-    assert cases > 50000 and nonzero > 20000
+    cases, nonzero, worst, whole = int(parts[1]), int(parts[2]), float(parts[3]), int(parts[4])
+    assert cases > 50000 and nonzero > 20000 and whole > 5000
     assert worst <= 1e-4
