@@ -113,17 +113,22 @@ __global__ __launch_bounds__(NT, chi_waves(NORB)) void chi_kernel(ChiArgs a) {
   const WT* w_p = static_cast<const WT*>(a.w) + (int64_t)np * NORB * nk;
   const float sc_n = a.w_scale ? a.w_scale[n] : 1.0f, sc_p = a.w_scale ? a.w_scale[np] : 1.0f;
 
-  // Stage the tile: eps_n at the point, eps_n' at the point + q, W = b_n(k) b_n'(k + q); reduce the
-  // ranges of eps, eps', eps' - eps and the largest |W|.
-  float r_emin = __builtin_huge_valf(), r_emax = -__builtin_huge_valf();
-  float r_pmin = __builtin_huge_valf(), r_pmax = -__builtin_huge_valf();
-  float r_dmin = __builtin_huge_valf(), r_dmax = -__builtin_huge_valf(), r_wmax = 0.0f, r_wmin = 0.0f;
-  for (int p = tid; p < NP; p += NT) {
+  // Stage the tile's energies: eps_n at the point, eps_n' at the point + q; reduce the ranges of eps,
+  // eps' and eps' - eps. Most (tile, band pair) units end here: no region can be occupied on one side
+  // and empty on the other, or eps' - eps stays outside the energy grid; their weights are never read.
+  auto point_k = [&](int p, int64_t& k, int64_t& kq) {
     const int pz = p % PZ, py = (p / PZ) % PY, px = p / (PZ * PY);
     const int i1 = wrap_index(x0 + px, a.n1), i2 = wrap_index(y0 + py, a.n2), i3 = wrap_index(z0 + pz, a.n3);
-    const int64_t k = ((int64_t)i1 * a.n2 + i2) * a.n3 + i3;
-    const int64_t kq = ((int64_t)wrap_index(i1 + a.q1, a.n1) * a.n2 + wrap_index(i2 + a.q2, a.n2)) * a.n3 +
-                       wrap_index(i3 + a.q3, a.n3);
+    k = ((int64_t)i1 * a.n2 + i2) * a.n3 + i3;
+    kq = ((int64_t)wrap_index(i1 + a.q1, a.n1) * a.n2 + wrap_index(i2 + a.q2, a.n2)) * a.n3 +
+         wrap_index(i3 + a.q3, a.n3);
+  };
+  float r_emin = __builtin_huge_valf(), r_emax = -__builtin_huge_valf();
+  float r_pmin = __builtin_huge_valf(), r_pmax = -__builtin_huge_valf();
+  float r_dmin = __builtin_huge_valf(), r_dmax = -__builtin_huge_valf();
+  for (int p = tid; p < NP; p += NT) {
+    int64_t k, kq;
+    point_k(p, k, kq);
     const float e = eps_n[k], ep = eps_p[kq];
     s_e[p] = e;
     s_ep[p] = ep;
@@ -135,27 +140,20 @@ __global__ __launch_bounds__(NT, chi_waves(NORB)) void chi_kernel(ChiArgs a) {
       r_dmin = fminf(r_dmin, ep - e);
       r_dmax = fmaxf(r_dmax, ep - e);
     }
-#pragma unroll
-    for (int m = 0; m < NORB; ++m) {
-      const float W = weight_value(w_n[(int64_t)m * nk + k], sc_n) * weight_value(w_p[(int64_t)m * nk + kq], sc_p);
-      s_W[p * NORB + m] = W;
-      r_wmax = fmaxf(r_wmax, fabsf(W));
-      r_wmin = fminf(r_wmin, W);
-    }
   }
   float red[8] = {wave_min_f(r_emin), wave_max_f(r_emax), wave_min_f(r_pmin), wave_max_f(r_pmax),
-                  wave_min_f(r_dmin), wave_max_f(r_dmax), wave_max_f(r_wmax), wave_min_f(r_wmin)};
+                  wave_min_f(r_dmin), wave_max_f(r_dmax), 0.0f, 0.0f};
   if ((tid & 63) == 0)
 #pragma unroll
-    for (int i = 0; i < 8; ++i) s_red[i * (NT / 64) + (tid >> 6)] = red[i];
+    for (int i = 0; i < 6; ++i) s_red[i * (NT / 64) + (tid >> 6)] = red[i];
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
+  for (int i = 0; i < 6; ++i) {
     float v = s_red[i * (NT / 64)];
 #pragma unroll
     for (int wv = 1; wv < NT / 64; ++wv) {
       const float x = s_red[i * (NT / 64) + wv];
-      v = (i == 0 || i == 2 || i == 4 || i == 7) ? fminf(v, x) : fmaxf(v, x);
+      v = (i == 0 || i == 2 || i == 4) ? fminf(v, x) : fmaxf(v, x);
     }
     red[i] = v;
   }
@@ -166,6 +164,34 @@ __global__ __launch_bounds__(NT, chi_waves(NORB)) void chi_kernel(ChiArgs a) {
   int J0, J1;
   range_window(red[4], red[5], a.e0, a.inv_de, a.ne, J0, J1);
   if (J0 > J1) return;
+
+  // The weights W = b_n(k) b_n'(k + q), with the largest |W| and the smallest W.
+  float r_wmax = 0.0f, r_wmin = 0.0f;
+  for (int p = tid; p < NP; p += NT) {
+    int64_t k, kq;
+    point_k(p, k, kq);
+#pragma unroll
+    for (int m = 0; m < NORB; ++m) {
+      const float W = weight_value(w_n[(int64_t)m * nk + k], sc_n) * weight_value(w_p[(int64_t)m * nk + kq], sc_p);
+      s_W[p * NORB + m] = W;
+      r_wmax = fmaxf(r_wmax, fabsf(W));
+      r_wmin = fminf(r_wmin, W);
+    }
+  }
+  r_wmax = wave_max_f(r_wmax);
+  r_wmin = wave_min_f(r_wmin);
+  if ((tid & 63) == 0) {
+    s_red[6 * (NT / 64) + (tid >> 6)] = r_wmax;
+    s_red[7 * (NT / 64) + (tid >> 6)] = r_wmin;
+  }
+  __syncthreads();
+  red[6] = s_red[6 * (NT / 64)];
+  red[7] = s_red[7 * (NT / 64)];
+#pragma unroll
+  for (int wv = 1; wv < NT / 64; ++wv) {
+    red[6] = fmaxf(red[6], s_red[6 * (NT / 64) + wv]);
+    red[7] = fminf(red[7], s_red[7 * (NT / 64) + wv]);
+  }
   const float wmax = red[6], wmin = red[7];
 
   const int cz = tid % TZ, cy = (tid / TZ) % TY, cx = tid / (TZ * TY);
@@ -359,16 +385,17 @@ __global__ __launch_bounds__(NT, chi_waves(NORB)) void chi_kernel(ChiArgs a) {
       }
       __syncthreads();
       // Second sweep: the queued regions, clipped at the two occupation boundaries into at most 3 x 3
-      // sub-tetrahedra. The lanes take (region, first piece, second piece) slots, so the pieces are
-      // shared out evenly; each slot redoes its region's planes and first clipping from LDS (nothing
-      // of the clipping stays live over a piece's energy loop) and leaves early if its piece does
-      // not exist.
+      // sub-tetrahedra. The lanes take (first piece, second piece, region) slots, piece-major: the
+      // first piece of every region exists, the others only for some, so the slots with work stay
+      // together and a wavefront whose slots hold no piece leaves early. Each slot redoes its region's
+      // planes and first clipping from LDS (nothing of the clipping stays live over a piece's energy
+      // loop) and leaves early if its piece does not exist.
       const int nq = s_qn;
       constexpr float I[4][4] = {{1.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 1.0f, 0.0f, 0.0f},
                                  {0.0f, 0.0f, 1.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 1.0f}};
 #pragma unroll 1
       for (int ip = tid; ip < 9 * nq; ip += NT) {
-        const int iq = ip / 9, piece = ip - 9 * iq;
+        const int piece = ip / nq, iq = ip - piece * nq;
         const int ia = piece / 3, ib = piece - 3 * ia;
         const int item = s_q[iq];
         const int it = item >> 4, t = (item >> 1) & 7, r = item & 1;
