@@ -385,9 +385,10 @@ __global__ __launch_bounds__(NT, chi_waves(NORB)) void chi_kernel(ChiArgs a) {
       }
       __syncthreads();
       // Second sweep: the queued regions, clipped at the two occupation boundaries into at most 3 x 3
-      // sub-tetrahedra. The lanes take (first piece, second piece, region) slots, piece-major: the
-      // first piece of every region exists, the others only for some, so the slots with work stay
-      // together and a wavefront whose slots hold no piece leaves early. Each slot redoes its region's
+      // sub-tetrahedra. The lanes take (first piece, second piece, region) slots, piece-major: a
+      // region's first slot holds a piece unless the region is empty, the others only for some
+      // regions, so the slots with work stay together and a wavefront whose slots hold no piece
+      // leaves early. Each slot redoes its region's
       // planes and first clipping from LDS (nothing of the clipping stays live over a piece's energy
       // loop) and leaves early if its piece does not exist.
       const int nq = s_qn;
