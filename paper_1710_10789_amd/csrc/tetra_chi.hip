@@ -73,7 +73,9 @@ __device__ __forceinline__ float wave_sum_f(float v) {
 
 // Waves per SIMD the kernel is held to. With nothing of the clipping live over a sub-tetrahedron's
 // energy loop it needs 100-140 VGPRs up to 8 orbitals (139 at 8: held to 4 waves it keeps 8 values in
-// scratch, 2.00 against 2.27 ms at 3 waves for the 64^3 x 8 x 8 x 500 workload) and up to 196 at 16.
+// scratch, 2.00 against 2.27 ms at 3 waves for the 64^3 x 8 x 8 x 500 workload) and up to 196 at 16
+// (held to 3 waves it keeps 30 values in scratch and still beats 2 waves: 4.68 against 5.18 ms for
+// 48^3 x 16 x 16 x 500).
 constexpr int chi_waves(int norb) { return norb <= 8 ? 4 : 3; }
 
 template <int NORB, typename WT>
