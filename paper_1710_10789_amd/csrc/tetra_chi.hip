@@ -341,8 +341,7 @@ __global__ __launch_bounds__(NT, chi_waves(NORB)) void chi_kernel(ChiArgs a) {
       __syncthreads();
       // First sweep, every lane on its own cube: the regions that are the whole tetrahedron, most of
       // them, as the forward kernel forms a DOS (the corners sorted with their points, the weights read
-      // in sorted order: no clipping, no parent-corner weights, nothing to put back per energy), and
-      // the other regions queued. The regions that need clipping lie where a band crosses E_F, in a
+      // in sorted order, no clipping), and the other regions queued. The regions that need clipping lie where a band crosses E_F, in a
       // few cubes of the tile; sharing them out over all lanes keeps them from holding one wavefront,
       // and the workgroup behind its barrier, for the whole pass.
       if (valid) {
