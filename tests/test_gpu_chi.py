@@ -5,7 +5,8 @@ Gate: max |S - S_ref| / max |S_ref| <= 1e-5 (FP32 arithmetic; the clipping at th
 FP32 on the kernel side). Cases: small and ragged grids (every tile shape on one of them), transfers of
 both signs and zero, one to sixteen orbitals, a symmetric transfer-energy grid (both signs of w),
 FP16 weights and complex amplitudes (against the oracle on the weights the kernel sees), non-finite
-energies, and the 64^3 x 8 x 8 workload with 500 transfer energies in full."""
+energies, bands that straddle E_F everywhere (every region clipped: the kernel's queue of regions to
+clip at its capacity), and the 64^3 x 8 x 8 workload with 500 transfer energies in full."""
 import numpy as np
 import pytest
 
@@ -158,3 +159,24 @@ def test_signed_weights_use_the_signed_accumulator(torch_dev, oracle_lib):
     got = _run(torch_dev, eps, w, grid, (2, 3, 1), ef, w0, dw, 100)
     assert np.abs(ref).max() > 0
     assert dos_err(got, ref) <= 1e-5
+
+
+def test_every_region_clipped(torch_dev, oracle_lib):
+    """Both bands a little random noise around E_F at every point: nearly every region of every
+    tetrahedron straddles a Fermi plane, so the kernel queues both regions of nearly all six
+    tetrahedra of every cube (its queue's capacity) and works the clipped pieces off in many rounds
+    of the whole workgroup; 16^3 grid, 2 bands, 3 orbitals, both signs of w."""
+    rng = np.random.default_rng(47)
+    grid = (16, 16, 16)
+    nb, norb, nk = 2, 3, 16 * 16 * 16
+    eps = (0.05 * rng.standard_normal((nb, nk))).astype(np.float32)
+    w = rng.random((nb, norb, nk)).astype(np.float32)
+    ef = 0.0
+    w0, dw = _grid_for(eps, 64, True)
+    print("[case] chi every region clipped 16^3 nb=2 norb=3", flush=True)
+    ref, nsub = oracle_lib.chi(eps, w, grid, (2, 1, 0), ef, w0, dw, 64)
+    got = _run(torch_dev, eps, w, grid, (2, 1, 0), ef, w0, dw, 64)
+    err = dos_err(got, ref)
+    print(f"[case] err {err:.3e}, {nsub} updates", flush=True)
+    assert np.abs(ref).max() > 0
+    assert err <= 1e-5
