@@ -262,11 +262,34 @@ tetra_status tetra_dos_binned(const tetra_desc* d, const float* eps, const void*
  *   flags    TETRA_TILE(shape) or 0 (TETRA_EXACT and TETRA_DETERMINISTIC give TETRA_ERR_UNSUPPORTED)
  * One workgroup per (tile, band pair): nb*nb*(tiles) must stay below 2^31 (TETRA_ERR_UNSUPPORTED).
  * A tetrahedron with a non-finite corner energy in either band contributes nothing for that pair.
- * Allocates nothing.
+ * Allocates nothing. Same as tetra_chi_spectral_ws with no workspace.
  */
 tetra_status tetra_chi_spectral(const tetra_desc* d, int q1, int q2, int q3, float e_fermi, const float* eps,
                                 const void* w, int wtype, const float* w_scale, float* out, unsigned flags,
                                 void* stream);
+
+/*
+ * Bytes of device workspace for tetra_chi_spectral_ws: 16 nb T, with T the tiles of the grid for the
+ * tile shape in flags (two energy ranges of 8 bytes per (tile, band)). 0 for invalid arguments.
+ * flags: TETRA_TILE(shape) or 0.
+ */
+size_t tetra_chi_spectral_workspace(const tetra_desc* d, unsigned flags);
+
+/*
+ * tetra_chi_spectral with a caller-owned workspace (device memory of at least
+ * tetra_chi_spectral_workspace(d, flags) bytes, 16-byte aligned (TETRA_ERR_ARG otherwise), contents
+ * ignored and overwritten, not used after the work on the stream ends). A first pass writes the
+ * energy range of every (tile, band) there, at the tile's points and at the points shifted by q, so
+ * that a (tile, band pair) unit whose bands cannot be occupied on one side of E_F and empty on the
+ * other, or whose range of eps' - eps misses the transfer-energy grid, leaves before loading anything
+ * (most units of a model with many bands). The tests bound the exact ones, so the result is the one
+ * tetra_chi_spectral computes (up to the order of the float atomics that add the units' partial
+ * sums). workspace NULL: tetra_chi_spectral. ws_bytes below the size: TETRA_ERR_WORKSPACE.
+ * Other arguments and errors as for tetra_chi_spectral. Allocates nothing.
+ */
+tetra_status tetra_chi_spectral_ws(const tetra_desc* d, int q1, int q2, int q3, float e_fermi, const float* eps,
+                                   const void* w, int wtype, const float* w_scale, float* out, unsigned flags,
+                                   void* workspace, size_t ws_bytes, void* stream);
 
 /* One problem of a batch: its descriptor and device buffers (same meaning as tetra_dos_forward). */
 typedef struct {

@@ -32,6 +32,7 @@ __all__ = [
     "nos_forward",
     "dos_binned",
     "chi_spectral",
+    "chi_workspace_bytes",
     "dos",
     "dos_batched",
     "batched_workspace_bytes",
@@ -128,6 +129,11 @@ def lib():
         L.tetra_dos_binned.restype = i
         L.tetra_chi_spectral.argtypes = [ctypes.POINTER(TetraDesc), i, i, i, ctypes.c_float, p, p, i, p, p, u, p]
         L.tetra_chi_spectral.restype = i
+        L.tetra_chi_spectral_workspace.argtypes = [ctypes.POINTER(TetraDesc), u]
+        L.tetra_chi_spectral_workspace.restype = ctypes.c_size_t
+        L.tetra_chi_spectral_ws.argtypes = [ctypes.POINTER(TetraDesc), i, i, i, ctypes.c_float, p, p, i, p, p, u, p,
+                                            ctypes.c_size_t, p]
+        L.tetra_chi_spectral_ws.restype = i
         L.tetra_dos_backward.argtypes = [ctypes.POINTER(TetraDesc), p, p, i, p, p, p, p, u, p]
         L.tetra_dos_backward.restype = i
         L.tetra_dos_backward_workspace.argtypes = [ctypes.POINTER(TetraDesc), u]
@@ -253,11 +259,24 @@ def dos_binned(eps, w, grid, e0, de, ne, *, w_scale=None, out=None, tile=None):
     return _integrated("tetra_dos_binned", eps, w, grid, e0, de, ne, w_scale, out, tile)
 
 
-def chi_spectral(eps, w, grid, q, e_fermi, w0, dw, nw, *, w_scale=None, out=None, tile=None):
+def chi_workspace_bytes(grid, nb, norb, w0, dw, nw, *, tile=None):
+    """Bytes of the workspace ``chi_spectral`` passes to ``tetra_chi_spectral_ws`` (the energy range of
+    every (tile, band) at k and at k + q)."""
+    d = make_desc(grid, nb, norb, w0, dw, nw)
+    return int(lib().tetra_chi_spectral_workspace(ctypes.byref(d), _tile_flag(tile)))
+
+
+def chi_spectral(eps, w, grid, q, e_fermi, w0, dw, nw, *, w_scale=None, out=None, tile=None, workspace=None,
+                 ranges=True):
     """Orbital-resolved susceptibility spectral weight ``S [nw, norb]`` (FP32) at transfer energies
     w_j = w0 + j*dw for the transfer ``q`` (three integers, grid steps) and Fermi energy ``e_fermi``:
     the imaginary part of the bare Lindhard susceptibility at zero temperature is ``-pi S``. Sums every
-    band pair (n, n') with weights b_n(k) b_n'(k + q). Arguments otherwise as for ``dos_forward``."""
+    band pair (n, n') with weights b_n(k) b_n'(k + q). Arguments otherwise as for ``dos_forward``.
+
+    ``ranges`` (default): ``tetra_chi_spectral_ws`` with a workspace (``workspace``, a uint8 tensor of
+    at least ``chi_workspace_bytes(...)`` bytes, or one taken from torch's allocator), whose first pass
+    lets the (tile, band pair) units that cannot contribute leave before loading anything;
+    ``ranges=False``: ``tetra_chi_spectral``."""
     torch = _torch()
     nk, nb, norb = _shapes(eps, w, grid)
     dev = eps.device
@@ -269,10 +288,19 @@ def chi_spectral(eps, w, grid, q, e_fermi, w0, dw, nw, *, w_scale=None, out=None
     _require(out, "out", (int(nw), norb), (torch.float32,), dev)
     q1, q2, q3 = (int(x) for x in q)
     d = make_desc(grid, nb, norb, w0, dw, nw)
-    st = lib().tetra_chi_spectral(ctypes.byref(d), q1, q2, q3, float(e_fermi), eps.data_ptr(), w.data_ptr(), wtype,
-                                  w_scale.data_ptr() if w_scale is not None else None, out.data_ptr(),
-                                  _tile_flag(tile), _stream_handle(dev))
-    _check("tetra_chi_spectral", st)
+    ws_ptr, ws_bytes = None, 0
+    if ranges:
+        need = int(lib().tetra_chi_spectral_workspace(ctypes.byref(d), _tile_flag(tile)))
+        if workspace is None:
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+        _check_workspace(workspace, need, dev)
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel()
+    elif workspace is not None:
+        raise ValueError("workspace is for ranges=True")
+    st = lib().tetra_chi_spectral_ws(ctypes.byref(d), q1, q2, q3, float(e_fermi), eps.data_ptr(), w.data_ptr(), wtype,
+                                     w_scale.data_ptr() if w_scale is not None else None, out.data_ptr(),
+                                     _tile_flag(tile), ws_ptr, ws_bytes, _stream_handle(dev))
+    _check("tetra_chi_spectral_ws", st)
     return out
 
 

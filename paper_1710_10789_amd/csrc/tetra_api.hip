@@ -199,9 +199,9 @@ tetra_status tetra_dos_binned(const tetra_desc* d, const float* eps, const void*
   return nos_entry(d, eps, w, wtype, w_scale, dos, flags, stream, true);
 }
 
-tetra_status tetra_chi_spectral(const tetra_desc* d, int q1, int q2, int q3, float e_fermi, const float* eps,
-                                const void* w, int wtype, const float* w_scale, float* out, unsigned flags,
-                                void* stream) {
+tetra_status tetra_chi_spectral_ws(const tetra_desc* d, int q1, int q2, int q3, float e_fermi, const float* eps,
+                                   const void* w, int wtype, const float* w_scale, float* out, unsigned flags,
+                                   void* workspace, size_t ws_bytes, void* stream) {
   tetra_status st = check_desc(d);
   if (st != TETRA_OK) return st;
   if (!eps || !w || !out) return TETRA_ERR_ARG;
@@ -212,8 +212,25 @@ tetra_status tetra_chi_spectral(const tetra_desc* d, int q1, int q2, int q3, flo
   if (shape >= tetra::kTileShapes) return TETRA_ERR_ARG;
   if (flags & (TETRA_EXACT | TETRA_DETERMINISTIC)) return TETRA_ERR_UNSUPPORTED;
   if (tetra::chi_units(*d, shape) > 2147483647 - 8) return TETRA_ERR_UNSUPPORTED;  // one workgroup per unit
+  if (workspace) {
+    if (ws_bytes < 8 * (size_t)tetra::chi_range_entries(*d, shape)) return TETRA_ERR_WORKSPACE;
+    if (reinterpret_cast<uintptr_t>(workspace) % 16 != 0) return TETRA_ERR_ARG;
+  }
   return hip_status(tetra::chi(*d, q1, q2, q3, e_fermi, eps, w, wtype, scale_of(wtype, w_scale), out, shape,
-                               (hipStream_t)stream));
+                               workspace, (hipStream_t)stream));
+}
+
+tetra_status tetra_chi_spectral(const tetra_desc* d, int q1, int q2, int q3, float e_fermi, const float* eps,
+                                const void* w, int wtype, const float* w_scale, float* out, unsigned flags,
+                                void* stream) {
+  return tetra_chi_spectral_ws(d, q1, q2, q3, e_fermi, eps, w, wtype, w_scale, out, flags, nullptr, 0, stream);
+}
+
+size_t tetra_chi_spectral_workspace(const tetra_desc* d, unsigned flags) {
+  if (check_desc(d) != TETRA_OK || (flags & ~(unsigned)TETRA_TILE_MASK)) return 0;
+  const int shape = (int)((flags & TETRA_TILE_MASK) >> 8);
+  if (shape >= tetra::kTileShapes) return 0;
+  return 8 * (size_t)tetra::chi_range_entries(*d, shape);
 }
 
 size_t tetra_dos_batched_workspace(const tetra_item* items, int n, int wtype, unsigned flags) {

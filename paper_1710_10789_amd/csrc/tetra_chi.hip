@@ -50,6 +50,9 @@ struct ChiArgs {
   float ef, e0, de, inv_de, V;
   int TX, TY, TZ;
   int t1, t2, t3, ntiles, nunits, per_xcd;
+  // Energy range (smallest, largest finite value) of every (tile, band): rows [0, nb) at the tile's
+  // points, rows [nb, 2 nb) at the points shifted by q; NULL where not computed.
+  const float2* ranges;
 };
 
 __device__ __forceinline__ int wrap_index(int v, int n) {
@@ -69,6 +72,58 @@ __device__ __forceinline__ float wave_max_f(float v) {
 __device__ __forceinline__ float wave_sum_f(float v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
+}
+
+// First pass of the workspace variant: one workgroup per (tile, band) writes the band's energy range
+// over the tile's grid points (the points a unit stages) and over the same points shifted by q.
+__global__ __launch_bounds__(NT) void chi_ranges_kernel(ChiArgs a) {
+  __shared__ float s_r[4 * (NT / 64)];
+  const int tile = blockIdx.x % a.ntiles, band = blockIdx.x / a.ntiles;
+  const int PY = a.TY + 1, PZ = a.TZ + 1, NP = (a.TX + 1) * PY * PZ;
+  const int tz = tile % a.t3, ty = (tile / a.t3) % a.t2, tx = tile / (a.t3 * a.t2);
+  const int x0 = tx * a.TX, y0 = ty * a.TY, z0 = tz * a.TZ;
+  const int64_t nk = (int64_t)a.n1 * a.n2 * a.n3;
+  const float* e_b = a.eps + (int64_t)band * nk;
+  float kmin = __builtin_huge_valf(), kmax = -__builtin_huge_valf(), qmin = kmin, qmax = kmax;
+  for (int p = threadIdx.x; p < NP; p += NT) {
+    const int pz = p % PZ, py = (p / PZ) % PY, px = p / (PZ * PY);
+    const int i1 = wrap_index(x0 + px, a.n1), i2 = wrap_index(y0 + py, a.n2), i3 = wrap_index(z0 + pz, a.n3);
+    const float e = e_b[((int64_t)i1 * a.n2 + i2) * a.n3 + i3];
+    const float eq = e_b[((int64_t)wrap_index(i1 + a.q1, a.n1) * a.n2 + wrap_index(i2 + a.q2, a.n2)) * a.n3 +
+                         wrap_index(i3 + a.q3, a.n3)];
+    if (__builtin_isfinite(e)) {
+      kmin = fminf(kmin, e);
+      kmax = fmaxf(kmax, e);
+    }
+    if (__builtin_isfinite(eq)) {
+      qmin = fminf(qmin, eq);
+      qmax = fmaxf(qmax, eq);
+    }
+  }
+  kmin = wave_min_f(kmin);
+  kmax = wave_max_f(kmax);
+  qmin = wave_min_f(qmin);
+  qmax = wave_max_f(qmax);
+  if ((threadIdx.x & 63) == 0) {
+    const int wv = threadIdx.x >> 6;
+    s_r[wv] = kmin;
+    s_r[(NT / 64) + wv] = kmax;
+    s_r[2 * (NT / 64) + wv] = qmin;
+    s_r[3 * (NT / 64) + wv] = qmax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int wv = 1; wv < NT / 64; ++wv) {
+      kmin = fminf(kmin, s_r[wv]);
+      kmax = fmaxf(kmax, s_r[(NT / 64) + wv]);
+      qmin = fminf(qmin, s_r[2 * (NT / 64) + wv]);
+      qmax = fmaxf(qmax, s_r[3 * (NT / 64) + wv]);
+    }
+    float2* r = const_cast<float2*>(a.ranges);
+    r[(int64_t)band * a.ntiles + tile] = make_float2(kmin, kmax);
+    r[(int64_t)(a.nb + band) * a.ntiles + tile] = make_float2(qmin, qmax);
+  }
 }
 
 // Waves per SIMD the kernel is held to. With nothing of the clipping live over a sub-tetrahedron's
@@ -115,6 +170,19 @@ __global__ __launch_bounds__(NT, chi_waves(NORB)) void chi_kernel(ChiArgs a) {
   const WT* w_p = static_cast<const WT*>(a.w) + (int64_t)np * NORB * nk;
   const float sc_n = a.w_scale ? a.w_scale[n] : 1.0f, sc_p = a.w_scale ? a.w_scale[np] : 1.0f;
 
+  // With the first pass's ranges a unit that cannot contribute leaves before loading anything: the
+  // tables bound the staged values (their ranges include points where only one band is finite), so
+  // these tests only ever let through units that the exact ones below then drop.
+  if (a.ranges) {
+    const float2 rk = a.ranges[(int64_t)n * a.ntiles + tile];
+    const float2 rq = a.ranges[(int64_t)(a.nb + np) * a.ntiles + tile];
+    if (!(rk.x <= rk.y) || !(rq.x <= rq.y)) return;  // no finite energy in one of the bands
+    if (!region_possible(0, rk.x, rk.y, rq.x, rq.y, a.ef) && !region_possible(1, rk.x, rk.y, rq.x, rq.y, a.ef))
+      return;
+    int K0, K1;
+    range_window(rq.x - rk.y, rq.y - rk.x, a.e0, a.inv_de, a.ne, K0, K1);
+    if (K0 > K1) return;
+  }
   // Stage the tile's energies: eps_n at the point, eps_n' at the point + q; reduce the ranges of eps,
   // eps' and eps' - eps. Most (tile, band pair) units end here: no region can be occupied on one side
   // and empty on the other, or eps' - eps stays outside the energy grid; their weights are never read.
@@ -534,8 +602,13 @@ int64_t chi_units(const tetra_desc& d, int shape) {
   return ntiles * d.nb * d.nb;
 }
 
+int64_t chi_range_entries(const tetra_desc& d, int shape) {
+  const TileShape sh = tile_shape(shape);
+  return 2 * (int64_t)d.nb * ((d.n1 + sh.x - 1) / sh.x) * ((d.n2 + sh.y - 1) / sh.y) * ((d.n3 + sh.z - 1) / sh.z);
+}
+
 hipError_t chi(const tetra_desc& d, int q1, int q2, int q3, float e_fermi, const float* eps, const void* w, int wtype,
-               const float* w_scale, float* out, int shape, hipStream_t s) {
+               const float* w_scale, float* out, int shape, void* ranges_ws, hipStream_t s) {
   ChiArgs a;
   a.eps = eps;
   a.w = w;
@@ -565,8 +638,13 @@ hipError_t chi(const tetra_desc& d, int q1, int q2, int q3, float e_fermi, const
   a.nunits = (int)chi_units(d, shape);
   a.per_xcd = (a.nunits + NXCD - 1) / NXCD;
   const int grid = a.per_xcd * NXCD;
+  a.ranges = static_cast<const float2*>(ranges_ws);
   hipError_t e = fill_zero(out, (int64_t)d.ne * d.norb, s);
   if (e != hipSuccess) return e;
+  if (ranges_ws) {
+    hipLaunchKernelGGL(chi_ranges_kernel, dim3(a.ntiles * d.nb), dim3(NT), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   switch (d.norb) {
 #define TETRA_CASE(N) \
   case N:             \

@@ -52,8 +52,11 @@ hipError_t backward(const tetra_desc& d, const float* eps, const void* w, int wt
 
 // Susceptibility spectral weight into out[ne][norb] (the energy grid of d is the transfer-energy
 // grid) for the transfer (q1, q2, q3) in grid steps and Fermi energy e_fermi; every band pair.
+// ranges_ws: NULL, or device memory for chi_range_entries(d, shape) float2 values (the first pass's
+// energy range of every (tile, band) at k and at k + q).
 int64_t chi_units(const tetra_desc& d, int shape);
+int64_t chi_range_entries(const tetra_desc& d, int shape);
 hipError_t chi(const tetra_desc& d, int q1, int q2, int q3, float e_fermi, const float* eps, const void* w, int wtype,
-               const float* w_scale, float* out, int shape, hipStream_t s);
+               const float* w_scale, float* out, int shape, void* ranges_ws, hipStream_t s);
 
 }  // namespace tetra

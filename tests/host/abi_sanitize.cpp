@@ -140,6 +140,16 @@ int main() {
          TETRA_ERR_WORKSPACE);
   EXPECT(tetra_dos_backward_ws(&d, F, V, TETRA_W_F32, noscale, F, F, F, 0, misaligned, need, nullptr),
          TETRA_ERR_ARG);
+  // susceptibility first pass: two 8-byte ranges per (tile, band), 2 x 2 x 2 tiles of 4 x 4 x 16, 2 bands
+  EXPECT(tetra_chi_spectral_workspace(&d, 0), (size_t)16 * 2 * 8);
+  EXPECT(tetra_chi_spectral_workspace(&d, TETRA_TILE(1)), (size_t)16 * 2 * 1 * 1 * 8);  // 1 x 1 x 8 tiles of 8 x 8 x 4
+  EXPECT(tetra_chi_spectral_workspace(&d, TETRA_EXACT), 0);
+  EXPECT(tetra_chi_spectral_ws(&d, 1, 0, 0, 0.0f, F, V, TETRA_W_F32, noscale, F, 0, V, 16 * 2 * 8 - 1, nullptr),
+         TETRA_ERR_WORKSPACE);
+  EXPECT(tetra_chi_spectral_ws(&d, 1, 0, 0, 0.0f, F, V, TETRA_W_F32, noscale, F, 0, misaligned, 1 << 20, nullptr),
+         TETRA_ERR_ARG);
+  EXPECT(tetra_chi_spectral_ws(&d, 1, 0, 0, NAN, F, V, TETRA_W_F32, noscale, F, 0, V, 1 << 20, nullptr),
+         TETRA_ERR_ARG);
   tetra_desc r = good();
   r.n3 = 31;  // ragged: no two-phase output
   EXPECT(tetra_dos_backward_workspace(&r, 0), 0);

@@ -181,6 +181,37 @@ def test_chi_rejects_bad_arguments(L):
     assert call(d=many) == -2
 
 
+def test_chi_workspace_sizes_and_checks(L):
+    """tetra_chi_spectral_workspace: 16 nb T bytes (two 8-byte energy ranges per (tile, band)), 0 for
+    bad arguments; tetra_chi_spectral_ws rejects a short or misaligned workspace before any launch and
+    validates the rest as tetra_chi_spectral does."""
+    shapes = [(4, 4, 16), (8, 8, 4), (4, 8, 8), (8, 4, 8), (4, 16, 4), (16, 4, 4)]
+    for sid, (a, b, c) in enumerate(shapes):
+        for grid in ((64, 64, 64), (9, 6, 21), (1, 1, 1)):
+            d = tetra.make_desc(grid, 3, 2, 0.0, 0.01, 100)
+            tiles = -(-grid[0] // a) * -(-grid[1] // b) * -(-grid[2] // c)
+            assert L.tetra_chi_spectral_workspace(ctypes.byref(d), sid << 8) == 16 * 3 * tiles, (sid, grid)
+            assert tetra.chi_workspace_bytes(grid, 3, 2, 0.0, 0.01, 100, tile=sid) == 16 * 3 * tiles
+    assert L.tetra_chi_spectral_workspace(ctypes.byref(good()), 1) == 0  # no exact accumulation here
+    assert L.tetra_chi_spectral_workspace(ctypes.byref(good()), 6 << 8) == 0  # no such tile shape
+    bad = good()
+    bad.nb = 0
+    assert L.tetra_chi_spectral_workspace(ctypes.byref(bad), 0) == 0
+    f = L.tetra_chi_spectral_ws
+    d = good()
+    need = L.tetra_chi_spectral_workspace(ctypes.byref(d), 0)
+    assert need > 0
+
+    def call(ws, ws_bytes, ef=0.0, eps=FAKE, flags=0):
+        return f(ctypes.byref(d), 1, 0, -1, ef, eps, FAKE, 0, None, FAKE, flags, ws, ws_bytes, None)
+
+    assert call(FAKE, need - 1) == -3  # too small
+    assert call(FAKE + 8, need) == -1  # misaligned
+    assert call(FAKE, need, ef=float("nan")) == -1
+    assert call(FAKE, need, eps=None) == -1
+    assert call(FAKE, need, flags=1) == -2
+
+
 def test_pack_f16_rejects_bad_arguments(L):
     f = L.tetra_pack_f16
     assert f(0, 2, 3, FAKE, FAKE, FAKE, None) == -1

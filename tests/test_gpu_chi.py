@@ -6,7 +6,9 @@ FP32 on the kernel side). Cases: small and ragged grids (every tile shape on one
 both signs and zero, one to sixteen orbitals, a symmetric transfer-energy grid (both signs of w),
 FP16 weights and complex amplitudes (against the oracle on the weights the kernel sees), non-finite
 energies, bands that straddle E_F everywhere (every region clipped: the kernel's queue of regions to
-clip at its capacity), and the 64^3 x 8 x 8 workload with 500 transfer energies in full."""
+clip at its capacity), and the 64^3 x 8 x 8 workload with 500 transfer energies in full. The binding
+calls tetra_chi_spectral_ws (a first pass of per-(tile, band) energy ranges); its result is also
+compared with tetra_chi_spectral's."""
 import numpy as np
 import pytest
 
@@ -180,3 +182,46 @@ def test_every_region_clipped(torch_dev, oracle_lib):
     print(f"[case] err {err:.3e}, {nsub} updates", flush=True)
     assert np.abs(ref).max() > 0
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("case", ["ragged", "clipped", "full"])
+def test_first_pass_ranges_match_the_plain_call(torch_dev, oracle_lib, case):
+    """tetra_chi_spectral_ws (a first pass writes every (tile, band)'s energy ranges; units that cannot
+    contribute leave before loading anything) against tetra_chi_spectral on the same inputs: equal
+    within the order of the float atomics that add the units' partial sums (1e-5 of the largest value;
+    a unit skipped wrongly moves its bins by far more), and the ranges path against the oracle."""
+    torch, dev = torch_dev
+    if case == "ragged":
+        grid, nb, q, symmetric = (9, 6, 21), 3, (4, -2, 7), True
+        eps, w = synth.band_structure(nb, 8, grid)
+        ef = float(np.float32(np.median(eps)))
+        nw = 120
+        w0, dw = _grid_for(eps, nw, symmetric)
+    elif case == "clipped":
+        rng = np.random.default_rng(53)
+        grid, q, nw = (16, 16, 8), (3, 0, 1), 64
+        eps = (0.05 * rng.standard_normal((2, 16 * 16 * 8))).astype(np.float32)
+        w = rng.random((2, 3, 16 * 16 * 8)).astype(np.float32)
+        ef = 0.0
+        w0, dw = _grid_for(eps, nw, True)
+    else:
+        c = synth.config("chi_k64_b8_w500")
+        grid, nw, q = c["grid"], c["nw"], c["q"]
+        eps, w = synth.band_structure(c["norb"], c["seed"], grid)
+        ef, w0, dw = synth.chi_grid(eps, nw)
+    import paper_1710_10789_amd as tetra
+
+    te, tw = torch.from_numpy(np.ascontiguousarray(eps)).to(dev), torch.from_numpy(np.ascontiguousarray(w)).to(dev)
+    print(f"[case] chi first-pass ranges, {case}: grid {grid} nb {eps.shape[0]} norb {w.shape[1]}", flush=True)
+    for tile in (0, 3):
+        plain = tetra.chi_spectral(te, tw, grid, q, ef, w0, dw, nw, tile=tile, ranges=False)
+        ws = torch.empty(tetra.chi_workspace_bytes(grid, eps.shape[0], w.shape[1], w0, dw, nw, tile=tile),
+                         dtype=torch.uint8, device=dev)
+        fast = tetra.chi_spectral(te, tw, grid, q, ef, w0, dw, nw, tile=tile, workspace=ws)
+        torch.cuda.synchronize()
+        a, b = fast.cpu().numpy().astype(np.float64), plain.cpu().numpy().astype(np.float64)
+        diff = np.abs(a - b).max() / np.abs(b).max()
+        print(f"[case] tile {tile}: ranges vs plain {diff:.2e}", flush=True)
+        assert np.abs(b).max() > 0 and diff <= 1e-5
+    ref, _ = oracle_lib.chi(eps, w, grid, q, ef, w0, dw, nw)
+    assert dos_err(a, ref) <= 1e-5
