@@ -625,7 +625,8 @@ def chi_record(args, torch, tetra, dev, with_oracle=True):
         rec["roofline"] = {"bound": "alu", "kernel": "chi_kernel", "achieved": achieved,
                            "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                            "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": load_traffic("chi_kernel"),
-                           "algorithmic_flops_per_launch": flops, "avg_launch_ms": ms}
+                           "algorithmic_flops_per_launch": flops, "avg_launch_ms": ms,
+                           "timed_over": "the whole call: zero fill, chi_ranges_kernel (first pass), chi_kernel"}
         rec["error_vs_fp64_oracle"] = float(np.abs(got - ref).max() / np.abs(ref).max())
         rec["cpu_baseline"] = {"value": dense / t_or, "unit": "updates/s", "cores": cores, "kind": "oracle",
                                "sample": f"the whole workload, one pass, FP64 ({t_or:.1f} s)"}
